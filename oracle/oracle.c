@@ -1,0 +1,532 @@
+/*
+ * oracle.c -- plain, slow CPU reference for multiple-double polynomial
+ * evaluation and differentiation at truncated power series.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with
+ * the HIP path (no headers, helpers or tables): both follow the same written
+ * specification of the multiple-double operations and of the operation
+ * order, independently.
+ *
+ * What it computes (Verschelde, "Accelerated polynomial evaluation and
+ * differentiation at power series in multiple double precision"):
+ *   p = a_0 + sum_k a_k * z_{i_1} * ... * z_{i_{n_k}}        (Section 4, eq. (3))
+ * and all partial derivatives dp/dz_i, where every product is the truncated
+ * convolution of eq. (1) (Section 2), in m-fold double arithmetic.
+ *
+ * Per monomial it runs the forward / backward / cross product recipe of
+ * Section 3 (statement list and the n=5 example, eq. (2)), with the index
+ * readings listed in the design notes: the forward chain multiplies by
+ * z_{i_j}; the cross product c_j uses b_{n-2-j}.  Contributions are added
+ * with the pairwise tree of Section 5 (adjacent pairs, odd element carried),
+ * in the order fixed by the worked example (Section 4, the two addition steps
+ * after eq. (5)).  Plain loops, no jobs, no layers.
+ *
+ * Multiple-double arithmetic (m limbs, limb 0 most significant) follows the
+ * project's specification, built from published error-free transformations:
+ *   two_sum  -- Knuth's branch-free TwoSum (6 flops, exact);
+ *   two_prod -- p = RN(a*b), e = fma(a, b, -p) (exact);
+ *   deposit  -- add a term into a per-level running sum S[lo], pushing each
+ *               exact error one level down; the last level adds plainly;
+ *   renorm   -- bottom-up TwoSum pass, then top-down TwoSum pass.
+ * Compile with -ffp-contract=off and without fast-math: every + - * is one
+ * IEEE binary64 round-to-nearest operation and fma() is the fused one.
+ *
+ * Parity pins: tests compare this file against exact rational arithmetic
+ * (Python fractions), closed forms and integer-exact cases; see tests/.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXM 10
+
+/* ---------------------------------------------------------------- md ops -- */
+
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double ss = a + b;
+    double bb = ss - a;
+    double err = (a - (ss - bb)) + (b - bb);
+    *s = ss;
+    *e = err;
+}
+
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double pp = a * b;
+    *e = fma(a, b, -pp);
+    *p = pp;
+}
+
+/* Add t into the level sums S[lo..m-1]: exact at levels lo..m-2, rounded at m-1. */
+static void deposit(int m, double *S, int lo, double t)
+{
+    for (int j = lo; j < m - 1; ++j)
+        two_sum(S[j], t, &S[j], &t);
+    S[m - 1] = S[m - 1] + t;
+}
+
+/* Turn level sums S[0..m-1] into an m-limb expansion r (value preserved exactly). */
+static void renorm(int m, const double *S, double *r)
+{
+    double u[MAXM];
+    if (m == 1) {
+        r[0] = S[0];
+        return;
+    }
+    double s = S[m - 1];
+    for (int j = m - 2; j >= 0; --j)
+        two_sum(S[j], s, &s, &u[j + 1]);
+    u[0] = s;
+    r[0] = u[0];
+    double e = u[1];
+    for (int j = 1; j <= m - 2; ++j)
+        two_sum(e, u[j + 1], &r[j], &e);
+    r[m - 1] = e;
+}
+
+/* z = x + y in m-double arithmetic; z may alias x or y. */
+static void md_add(int m, const double *x, const double *y, double *z)
+{
+    double S[MAXM];
+    for (int k = 0; k < m; ++k)
+        S[k] = x[k];
+    for (int k = 0; k < m; ++k)
+        deposit(m, S, k, y[k]);
+    renorm(m, S, z);
+}
+
+/* z = x * y in m-double arithmetic (truncated product); z may alias x or y. */
+static void md_mul(int m, const double *x, const double *y, double *z)
+{
+    double S[MAXM], E[MAXM], p, e;
+    /* level k <= m-2 starts with the exact product x_0*y_k */
+    for (int k = 0; k <= m - 2; ++k)
+        two_prod(x[0], y[k], &S[k], &E[k]);
+    /* last level: the products of level m-1, then those of level m */
+    S[m - 1] = x[0] * y[m - 1];
+    for (int i = 1; i <= m - 1; ++i)
+        S[m - 1] = fma(x[i], y[m - 1 - i], S[m - 1]);
+    for (int i = 1; i <= m - 1; ++i)
+        S[m - 1] = fma(x[i], y[m - i], S[m - 1]);
+    /* the low parts of x_0*y_k belong one level down */
+    for (int k = 0; k <= m - 2; ++k)
+        deposit(m, S, k + 1, E[k]);
+    /* the remaining exact products x_i*y_{k-i}, i >= 1, of levels 1..m-2 */
+    for (int k = 1; k <= m - 2; ++k) {
+        for (int i = 1; i <= k; ++i) {
+            two_prod(x[i], y[k - i], &p, &e);
+            deposit(m, S, k, p);
+            deposit(m, S, k + 1, e);
+        }
+    }
+    renorm(m, S, z);
+}
+
+/* ------------------------------------------------------------ series ops -- */
+/* A series is (d+1) coefficients of m limbs: s[c*m + l]. */
+
+/* z = x * y truncated at degree d (Section 2, eq. (1)): for each k,
+ * z_k = x_0*y_k, then z_k += x_i*y_{k-i} for i = 1..k in increasing i.
+ * z may alias x or y (the in-place update b := b * a of Section 3). */
+static void conv(int m, int d, const double *x, const double *y, double *z, double *tmp)
+{
+    double p[MAXM];
+    for (int k = 0; k <= d; ++k) {
+        double *acc = tmp + (size_t)k * m;
+        md_mul(m, x, y + (size_t)k * m, acc);
+        for (int i = 1; i <= k; ++i) {
+            md_mul(m, x + (size_t)i * m, y + (size_t)(k - i) * m, p);
+            md_add(m, acc, p, acc);
+        }
+    }
+    memcpy(z, tmp, sizeof(double) * (size_t)(d + 1) * m);
+}
+
+/* upd := upd + inp, coefficientwise (Section 2, last paragraph; Section 5 addition job). */
+static void series_add(int m, int d, double *upd, const double *inp)
+{
+    for (int k = 0; k <= d; ++k)
+        md_add(m, upd + (size_t)k * m, inp + (size_t)k * m, upd + (size_t)k * m);
+}
+
+/* ---------------------------------------------------------- layout glue -- */
+
+/* planar [m][count][d+1] -> series-major [count][(d+1)*m] */
+static void from_planar(int m, int d, int count, const double *src, double *dst)
+{
+    for (int s = 0; s < count; ++s)
+        for (int c = 0; c <= d; ++c)
+            for (int l = 0; l < m; ++l)
+                dst[((size_t)s * (d + 1) + c) * m + l] = src[((size_t)l * count + s) * (d + 1) + c];
+}
+
+static void to_planar(int m, int d, int count, int idx, const double *ser, double *dst)
+{
+    for (int c = 0; c <= d; ++c)
+        for (int l = 0; l < m; ++l)
+            dst[((size_t)l * count + idx) * (d + 1) + c] = ser[(size_t)c * m + l];
+}
+
+/* --------------------------------------------------------- monomial AD -- */
+
+/*
+ * Evaluate and differentiate one monomial a * z_{v[0]} * ... * z_{v[nk-1]}
+ * (Section 3, with the readings noted above).  Writes the value series to
+ * val and the partial derivative with respect to z_{v[j]} to der[j].
+ * Z holds the n input series (series-major).  Work arrays: f, b, c of
+ * nk series each, tmp one series.
+ */
+static void monomial(int m, int d, int nk, const int *v, const double *a, const double *Z,
+                     double *val, double **der, double *f, double *b, double *c, double *tmp)
+{
+    const size_t S = (size_t)(d + 1) * m;
+#define ZS(idx) (Z + (size_t)(idx) * S)
+#define F(j) (f + (size_t)((j) - 1) * S)  /* 1-based as in the paper */
+#define B(j) (b + (size_t)((j) - 1) * S)
+#define C(j) (c + (size_t)((j) - 1) * S)
+#define I(j) (v[(j) - 1])                  /* i_j, 1-based position */
+    const int n = nk;
+    if (n == 1) {
+        conv(m, d, a, ZS(I(1)), F(1), tmp);
+        memcpy(val, F(1), sizeof(double) * S);
+        memcpy(der[0], a, sizeof(double) * S);
+        return;
+    }
+    /* forward products: f_1 = a * z_{i_1}; f_j = f_{j-1} * z_{i_j} */
+    conv(m, d, a, ZS(I(1)), F(1), tmp);
+    for (int j = 2; j <= n; ++j)
+        conv(m, d, F(j - 1), ZS(I(j)), F(j), tmp);
+    if (n == 2) {
+        /* b_1 = z_{i_2} * a (the n_k = 2 case of Section 5) */
+        conv(m, d, ZS(I(2)), a, B(1), tmp);
+        memcpy(val, F(2), sizeof(double) * S);
+        memcpy(der[0], B(1), sizeof(double) * S);
+        memcpy(der[1], F(1), sizeof(double) * S);
+        return;
+    }
+    /* backward products: b_1 = z_{i_n} * z_{i_{n-1}}; b_j = b_{j-1} * z_{i_{n-j}};
+       then b_{n-2} := b_{n-2} * a */
+    conv(m, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);
+    for (int j = 2; j <= n - 2; ++j)
+        conv(m, d, B(j - 1), ZS(I(n - j)), B(j), tmp);
+    conv(m, d, B(n - 2), a, B(n - 2), tmp);
+    /* cross products: c_j = f_j * b_{n-2-j} for j = 1..n-3; c_{n-2} = f_{n-2} * z_{i_n} */
+    for (int j = 1; j <= n - 3; ++j)
+        conv(m, d, F(j), B(n - 2 - j), C(j), tmp);
+    conv(m, d, F(n - 2), ZS(I(n)), C(n - 2), tmp);
+    /* value f_n; d/dz_{i_1} = b_{n-2}; d/dz_{i_{j+1}} = c_j; d/dz_{i_n} = f_{n-1} */
+    memcpy(val, F(n), sizeof(double) * S);
+    memcpy(der[0], B(n - 2), sizeof(double) * S);
+    for (int j = 1; j <= n - 2; ++j)
+        memcpy(der[j], C(j), sizeof(double) * S);
+    memcpy(der[n - 1], F(n - 1), sizeof(double) * S);
+#undef ZS
+#undef F
+#undef B
+#undef C
+#undef I
+}
+
+/*
+ * Pairwise tree sum of a list of series (Section 5, addition jobs):
+ * in each round, element 2p+1 := element 2p+1 + element 2p for every pair,
+ * the survivors are the odd-positioned elements plus a carried last element
+ * when the count is odd.  The result ends in the last element of the list.
+ */
+static void tree_sum(int m, int d, int len, double **items)
+{
+    int r = len;
+    double **live = (double **)malloc(sizeof(double *) * (size_t)(len > 0 ? len : 1));
+    for (int i = 0; i < len; ++i)
+        live[i] = items[i];
+    while (r > 1) {
+        int w = 0;
+        for (int p = 0; p < r / 2; ++p) {
+            series_add(m, d, live[2 * p + 1], live[2 * p]);
+            live[w++] = live[2 * p + 1];
+        }
+        if (r % 2)
+            live[w++] = live[r - 1];
+        r = w;
+    }
+    free(live);
+}
+
+/* The schedule of tree_sum as pairs (input index, updated index) per round. */
+int oracle_tree_schedule(int len, int *pairs, int *round_sizes, int max_rounds)
+{
+    int *live = (int *)malloc(sizeof(int) * (size_t)(len > 0 ? len : 1));
+    int r = len, np = 0, nr = 0;
+    for (int i = 0; i < len; ++i)
+        live[i] = i;
+    while (r > 1) {
+        int w = 0;
+        if (nr >= max_rounds) {
+            free(live);
+            return -1;
+        }
+        round_sizes[nr] = r / 2;
+        for (int p = 0; p < r / 2; ++p) {
+            pairs[2 * np] = live[2 * p];
+            pairs[2 * np + 1] = live[2 * p + 1];
+            ++np;
+            live[w++] = live[2 * p + 1];
+        }
+        if (r % 2)
+            live[w++] = live[r - 1];
+        r = w;
+        ++nr;
+    }
+    free(live);
+    return nr;
+}
+
+/* ------------------------------------------------------------ the oracle -- */
+
+static int check_support(int n, int N, const int *nvars, const int *vars)
+{
+    size_t pos = 0;
+    if (n < 0 || N < 0)
+        return -1;
+    for (int k = 0; k < N; ++k) {
+        if (nvars[k] < 1 || nvars[k] > n)
+            return -1;
+        for (int j = 0; j < nvars[k]; ++j) {
+            int vj = vars[pos + j];
+            if (vj < 0 || vj >= n)
+                return -1;
+            if (j > 0 && vj <= vars[pos + j - 1])
+                return -1;
+        }
+        pos += nvars[k];
+    }
+    return 0;
+}
+
+/*
+ * value [m][d+1], grad [m][n][d+1]; coeff [m][N+1][d+1] (a_0 first); z [m][n][d+1].
+ * If monos is not NULL it receives, per monomial k, the value series
+ * prod_j z_{i_j} * a_k (the forward product f_{k,n_k}) in planar [m][N][d+1].
+ * nthreads <= 0 leaves the OpenMP default.  Returns 0, or -1 on a bad support.
+ */
+int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int *vars,
+                         const double *coeff, const double *z, double *value, double *grad,
+                         int nthreads)
+{
+    if (m < 1 || m > MAXM || d < 0 || check_support(n, N, nvars, vars))
+        return -1;
+    const size_t S = (size_t)(d + 1) * m;
+    size_t total = 0;
+    size_t *start = (size_t *)malloc(sizeof(size_t) * (size_t)(N + 1));
+    for (int k = 0; k < N; ++k) {
+        start[k] = total;
+        total += (size_t)nvars[k];
+    }
+    start[N] = total;
+    double *A = (double *)malloc(sizeof(double) * S * (size_t)(N + 1));
+    double *Z = (double *)malloc(sizeof(double) * S * (size_t)(n > 0 ? n : 1));
+    double *vals = (double *)malloc(sizeof(double) * S * (size_t)(N + 1));
+    double *ders = (double *)malloc(sizeof(double) * S * (total > 0 ? total : 1));
+    from_planar(m, d, N + 1, coeff, A);
+    from_planar(m, d, n, z, Z);
+    /* value list starts with a_0 */
+    memcpy(vals, A, sizeof(double) * S);
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        int nmax = 1;
+        for (int k = 0; k < N; ++k)
+            if (nvars[k] > nmax)
+                nmax = nvars[k];
+        double *work = (double *)malloc(sizeof(double) * S * (size_t)(3 * nmax + 1));
+        double **der = (double **)malloc(sizeof(double *) * (size_t)nmax);
+#pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < N; ++k) {
+            int nk = nvars[k];
+            for (int j = 0; j < nk; ++j)
+                der[j] = ders + (start[k] + (size_t)j) * S;
+            monomial(m, d, nk, vars + start[k], A + (size_t)(k + 1) * S, Z, vals + (size_t)(k + 1) * S, der,
+                     work, work + S * (size_t)nmax, work + 2 * S * (size_t)nmax, work + 3 * S * (size_t)nmax);
+        }
+        free(work);
+        free(der);
+    }
+    /* value: tree over [a_0, f_{1,n_1}, ..., f_{N,n_N}] */
+    {
+        double **items = (double **)malloc(sizeof(double *) * (size_t)(N + 1));
+        for (int k = 0; k <= N; ++k)
+            items[k] = vals + (size_t)k * S;
+        tree_sum(m, d, N + 1, items);
+        to_planar(m, d, 1, 0, items[N], value);
+        free(items);
+    }
+    /* gradient: list i holds the d/dz_i contributions in increasing monomial order */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i) {
+        int len = 0;
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < nvars[k]; ++j)
+                if (vars[start[k] + j] == i)
+                    ++len;
+        if (len == 0) {
+            for (int l = 0; l < m; ++l)
+                for (int c = 0; c <= d; ++c)
+                    grad[((size_t)l * n + i) * (d + 1) + c] = 0.0;
+            continue;
+        }
+        double **items = (double **)malloc(sizeof(double *) * (size_t)len);
+        int w = 0;
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < nvars[k]; ++j)
+                if (vars[start[k] + j] == i)
+                    items[w++] = ders + (start[k] + (size_t)j) * S;
+        tree_sum(m, d, len, items);
+        to_planar(m, d, n, i, items[len - 1], grad);
+        free(items);
+    }
+    free(start);
+    free(A);
+    free(Z);
+    free(vals);
+    free(ders);
+    return 0;
+}
+
+/*
+ * One monomial's raw products, for sampled checks at sizes where the whole
+ * oracle is too slow: out receives the value series and the nk partial
+ * derivative series of monomial a * prod z_{v[j]}, planar [m][nk+1][d+1]
+ * (value first, then d/dz_{v[0]}, ...).
+ */
+int oracle_monomial(int m, int d, int n, int nk, const int *v, const double *a /* [m][d+1] */,
+                    const double *z /* [m][n][d+1] */, double *out)
+{
+    if (m < 1 || m > MAXM || d < 0 || nk < 1 || nk > n)
+        return -1;
+    for (int j = 0; j < nk; ++j)
+        if (v[j] < 0 || v[j] >= n || (j > 0 && v[j] <= v[j - 1]))
+            return -1;
+    const size_t S = (size_t)(d + 1) * m;
+    double *A = (double *)malloc(sizeof(double) * S);
+    double *Z = (double *)malloc(sizeof(double) * S * (size_t)n);
+    double *res = (double *)malloc(sizeof(double) * S * (size_t)(nk + 1));
+    double *work = (double *)malloc(sizeof(double) * S * (size_t)(3 * nk + 1));
+    double **der = (double **)malloc(sizeof(double *) * (size_t)nk);
+    from_planar(m, d, 1, a, A);
+    from_planar(m, d, n, z, Z);
+    for (int j = 0; j < nk; ++j)
+        der[j] = res + (size_t)(j + 1) * S;
+    monomial(m, d, nk, v, A, Z, res, der, work, work + S * (size_t)nk, work + 2 * S * (size_t)nk,
+             work + 3 * S * (size_t)nk);
+    for (int j = 0; j <= nk; ++j)
+        to_planar(m, d, nk + 1, j, res + (size_t)j * S, out);
+    free(A);
+    free(Z);
+    free(res);
+    free(work);
+    free(der);
+    return 0;
+}
+
+/* ---------------------------------------------- elementwise entry points -- */
+/* x, y, z planar [m][count]; op 0 = add, 1 = mul. */
+int oracle_md_op(int op, int m, long count, const double *x, const double *y, double *z)
+{
+    if (m < 1 || m > MAXM || count < 0 || op < 0 || op > 1)
+        return -1;
+    for (long i = 0; i < count; ++i) {
+        double a[MAXM], b[MAXM], r[MAXM];
+        for (int l = 0; l < m; ++l) {
+            a[l] = x[(size_t)l * count + i];
+            b[l] = y[(size_t)l * count + i];
+        }
+        if (op == 0)
+            md_add(m, a, b, r);
+        else
+            md_mul(m, a, b, r);
+        for (int l = 0; l < m; ++l)
+            z[(size_t)l * count + i] = r[l];
+    }
+    return 0;
+}
+
+/* z = x * y truncated at degree d; planar [m][d+1]. */
+int oracle_conv(int m, int d, const double *x, const double *y, double *z)
+{
+    if (m < 1 || m > MAXM || d < 0)
+        return -1;
+    const size_t S = (size_t)(d + 1) * m;
+    double *X = (double *)malloc(sizeof(double) * S), *Y = (double *)malloc(sizeof(double) * S);
+    double *Zs = (double *)malloc(sizeof(double) * S), *T = (double *)malloc(sizeof(double) * S);
+    from_planar(m, d, 1, x, X);
+    from_planar(m, d, 1, y, Y);
+    conv(m, d, X, Y, Zs, T);
+    to_planar(m, d, 1, 0, Zs, z);
+    free(X);
+    free(Y);
+    free(Zs);
+    free(T);
+    return 0;
+}
+
+/* The two_sum / two_prod transforms themselves, planar [count]. */
+int oracle_eft(int op, long count, const double *a, const double *b, double *hi, double *lo)
+{
+    for (long i = 0; i < count; ++i) {
+        if (op == 0)
+            two_sum(a[i], b[i], &hi[i], &lo[i]);
+        else
+            two_prod(a[i], b[i], &hi[i], &lo[i]);
+    }
+    return 0;
+}
+
+/*
+ * Operation counts of md_add and md_mul for m limbs, obtained by walking the
+ * same loops as above and counting instead of computing.
+ * counts[0..3] = {add/sub, mul, fma, two_sum calls} for op (0 add, 1 mul).
+ */
+int oracle_op_counts(int op, int m, long *counts)
+{
+    long add = 0, mul = 0, fmas = 0, ts = 0;
+    if (m < 1 || m > MAXM)
+        return -1;
+#define TS() (ts++, add += 6)
+#define DEP(lo) do { for (int j_ = (lo); j_ < m - 1; ++j_) TS(); add += 1; } while (0)
+    if (op == 0) {
+        for (int k = 0; k < m; ++k)
+            DEP(k);
+    } else {
+        for (int k = 0; k <= m - 2; ++k) { mul += 1; fmas += 1; }
+        mul += 1;
+        fmas += 2 * (m - 1);
+        for (int k = 0; k <= m - 2; ++k)
+            DEP(k + 1);
+        for (int k = 1; k <= m - 2; ++k)
+            for (int i = 1; i <= k; ++i) {
+                mul += 1; fmas += 1;
+                DEP(k);
+                DEP(k + 1);
+            }
+    }
+    if (m > 1) {
+        for (int j = m - 2; j >= 0; --j) TS();
+        for (int j = 1; j <= m - 2; ++j) TS();
+    }
+#undef TS
+#undef DEP
+    counts[0] = add;
+    counts[1] = mul;
+    counts[2] = fmas;
+    counts[3] = ts;
+    return 0;
+}

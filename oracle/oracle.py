@@ -1,0 +1,136 @@
+"""ctypes wrapper around oracle/liboracle.so (see oracle.c for what it computes).
+
+TEST INFRASTRUCTURE ONLY.  All arrays are float64 numpy arrays in the
+limb-planar layouts of the C file: series batches [m][count][d+1].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def bind(path):
+    """Load an oracle shared library from ``path`` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    L.oracle_eval_and_diff.argtypes = [ctypes.c_int] * 4 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
+    L.oracle_monomial.argtypes = [ctypes.c_int] * 4 + [_ip, _dp, _dp, _dp]
+    L.oracle_md_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
+    L.oracle_conv.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+    L.oracle_eft.argtypes = [ctypes.c_int, ctypes.c_long, _dp, _dp, _dp, _dp]
+    L.oracle_op_counts.argtypes = [ctypes.c_int, ctypes.c_int, _lp]
+    L.oracle_tree_schedule.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int]
+    return L
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _LIB = bind(path)
+    return _LIB
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def eval_and_diff(m, d, n, nvars, vars_, coeff, z, nthreads=0, L=None):
+    """Return (value [m][d+1], grad [m][n][d+1]).  ``L``: an alternative library from bind()."""
+    nvars, vars_ = _i32(nvars), _i32(vars_)
+    N = int(nvars.shape[0])
+    coeff, z = _f64(coeff), _f64(z)
+    assert coeff.shape == (m, N + 1, d + 1), coeff.shape
+    assert z.shape == (m, n, d + 1), z.shape
+    value = np.empty((m, d + 1))
+    grad = np.empty((m, n, d + 1))
+    rc = (L or lib()).oracle_eval_and_diff(m, d, n, N, _i(nvars), _i(vars_), _d(coeff), _d(z), _d(value), _d(grad),
+                                    int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid polynomial description")
+    return value, grad
+
+
+def eval_workload(w, nthreads=0, L=None):
+    return eval_and_diff(w.m, w.d, w.n, w.nvars, w.vars, w.coeff, w.z, nthreads, L)
+
+
+def monomial(m, d, n, v, a, z):
+    """Value and partials of a * prod z_v as [m][nk+1][d+1] (value first)."""
+    v = _i32(v)
+    nk = int(v.shape[0])
+    a, z = _f64(a), _f64(z)
+    assert a.shape == (m, d + 1) and z.shape == (m, n, d + 1)
+    out = np.empty((m, nk + 1, d + 1))
+    if lib().oracle_monomial(m, d, n, nk, _i(v), _d(a), _d(z), _d(out)) != 0:
+        raise ValueError("oracle: invalid monomial")
+    return out
+
+
+def md_op(op, x, y):
+    """op 'add' or 'mul' on planar [m][count] arrays."""
+    x, y = _f64(x), _f64(y)
+    m, count = x.shape
+    z = np.empty_like(x)
+    if lib().oracle_md_op({"add": 0, "mul": 1}[op], m, count, _d(x), _d(y), _d(z)) != 0:
+        raise ValueError("oracle: bad md op")
+    return z
+
+
+def conv(x, y):
+    """Truncated product of two series, planar [m][d+1]."""
+    x, y = _f64(x), _f64(y)
+    m, d1 = x.shape
+    z = np.empty_like(x)
+    if lib().oracle_conv(m, d1 - 1, _d(x), _d(y), _d(z)) != 0:
+        raise ValueError("oracle: bad conv")
+    return z
+
+
+def eft(op, a, b):
+    a, b = _f64(a), _f64(b)
+    hi, lo = np.empty_like(a), np.empty_like(a)
+    lib().oracle_eft({"two_sum": 0, "two_prod": 1}[op], a.size, _d(a), _d(b), _d(hi), _d(lo))
+    return hi, lo
+
+
+def op_counts(op, m):
+    """{add, mul, fma, two_sum} double-operation counts of one md op."""
+    c = np.zeros(4, dtype=np.int64)
+    lib().oracle_op_counts({"add": 0, "mul": 1}[op], m, c.ctypes.data_as(_lp))
+    return dict(add=int(c[0]), mul=int(c[1]), fma=int(c[2]), two_sum=int(c[3]))
+
+
+def tree_schedule(length):
+    """Rounds of (input index, updated index) pairs of the pairwise tree sum."""
+    pairs = np.zeros(2 * max(length, 1), dtype=np.int32)
+    sizes = np.zeros(64, dtype=np.int32)
+    nr = lib().oracle_tree_schedule(int(length), _i(pairs), _i(sizes), 64)
+    out, pos = [], 0
+    for r in range(nr):
+        out.append([(int(pairs[2 * (pos + p)]), int(pairs[2 * (pos + p) + 1])) for p in range(sizes[r])])
+        pos += int(sizes[r])
+    return out

@@ -1,0 +1,96 @@
+"""Exact rational reference (Python fractions) for the oracle's pins.
+
+A multiple double x = (x_0, ..., x_{m-1}) denotes the exact rational sum of
+its limbs.  Everything here is exact: truncated power-series products
+(eq. (1) of the paper) and the polynomial of eq. (3) with its gradient,
+written directly from the definitions, with no ordering or rounding.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+
+def md_value(limbs) -> Fraction:
+    """Exact value of one multiple double given its limbs."""
+    return sum((Fraction(float(v)) for v in limbs), Fraction(0))
+
+
+def planar_to_exact(arr):
+    """[m][count][d+1] planar limbs -> list (count) of lists (d+1) of Fractions."""
+    m, count, d1 = arr.shape
+    return [[md_value(arr[:, s, c]) for c in range(d1)] for s in range(count)]
+
+
+def series_to_exact(arr):
+    """[m][d+1] -> list of Fractions."""
+    return [md_value(arr[:, c]) for c in range(arr.shape[1])]
+
+
+def smul(x, y):
+    """Truncated product of two exact series of equal length."""
+    d1 = len(x)
+    return [sum((x[i] * y[k - i] for i in range(k + 1)), Fraction(0)) for k in range(d1)]
+
+
+def sadd(x, y):
+    return [a + b for a, b in zip(x, y)]
+
+
+def poly_exact(supports, a, z):
+    """Exact value and gradient of p = a_0 + sum_k a_k prod_{j in S_k} z_j.
+
+    a: list of N+1 exact series (a_0 first); z: list of n exact series.
+    Returns (value, [grad_0, ..., grad_{n-1}]).
+    """
+    d1 = len(a[0])
+    zero = [Fraction(0)] * d1
+    value = list(a[0])
+    grad = [list(zero) for _ in z]
+    for k, sup in enumerate(supports):
+        term = list(a[k + 1])
+        for v in sup:
+            term = smul(term, z[v])
+        value = sadd(value, term)
+        for i in sup:
+            g = list(a[k + 1])
+            for v in sup:
+                if v != i:
+                    g = smul(g, z[v])
+            grad[i] = sadd(grad[i], g)
+    return value, grad
+
+
+def poly_magnitude(supports, a, z):
+    """The same computation on |coefficients|: the magnitude series used by the error bound."""
+    aa = [[abs(c) for c in s] for s in a]
+    zz = [[abs(c) for c in s] for s in z]
+    return poly_exact(supports, aa, zz)
+
+
+def workload_exact(w):
+    """Exact value/gradient and magnitudes for a workloads.Workload."""
+    a = planar_to_exact(w.coeff)
+    z = planar_to_exact(w.z)
+    sup = w.supports()
+    return poly_exact(sup, a, z), poly_magnitude(sup, a, z)
+
+
+def bound(m: int, d: int) -> Fraction:
+    """Relative bound 4(d+1) 2^(-52m) per coefficient, relative to the magnitude series."""
+    return Fraction(4 * (d + 1), 2 ** (52 * m))
+
+
+def max_scaled_error(got_planar, exact, mag):
+    """max_k |got_k - exact_k| / mag_k over coefficients with mag_k > 0 (got: [m][d+1])."""
+    worst = Fraction(0)
+    for c in range(got_planar.shape[1]):
+        g = md_value(got_planar[:, c])
+        err = abs(g - exact[c])
+        if mag[c] == 0:
+            if err != 0:
+                return Fraction(10 ** 9)
+            continue
+        worst = max(worst, err / mag[c])
+    return worst

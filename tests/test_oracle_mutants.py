@@ -1,0 +1,84 @@
+"""The oracle's pins are sensitive: plant one plausible mistake at a time in a
+copy of the oracle (on the CPU), rebuild it, and check that the exact
+rational pins reject it.  The mistakes cover a wrong variable index, a wrong
+backward-product index (including the literal index printed in Section 3's
+statement list, which the design reads as b_{n-2-j}), dropped terms in the
+multiple-double operations, a sign error in two_sum, a dropped carry in the
+addition tree and a mis-assigned partial derivative.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import exact_ref as E
+from oracle import build as obuild
+from oracle import oracle as O
+from paper_2101_10881_amd import workloads as W
+
+MUTANTS = {
+    "forward_chain_wrong_variable": ("conv(m, d, F(j - 1), ZS(I(j)), F(j), tmp);",
+                                     "conv(m, d, F(j - 1), ZS(I(j - 1)), F(j), tmp);"),
+    "cross_product_literal_index": ("conv(m, d, F(j), B(n - 2 - j), C(j), tmp);",
+                                    "conv(m, d, F(j), B(n - 3 - j), C(j), tmp);"),
+    "cross_product_off_by_one": ("conv(m, d, F(j), B(n - 2 - j), C(j), tmp);",
+                                 "conv(m, d, F(j), B(n - 1 - j), C(j), tmp);"),
+    "backward_start_wrong": ("conv(m, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);",
+                             "conv(m, d, ZS(I(n)), ZS(I(n - 2)), B(1), tmp);"),
+    "md_add_drops_last_limb": ("for (int k = 0; k < m; ++k)\n        deposit(m, S, k, y[k]);",
+                               "for (int k = 0; k < m - 1; ++k)\n        deposit(m, S, k, y[k]);"),
+    "md_mul_drops_low_parts": ("deposit(m, S, k + 1, E[k]);", "(void)E[k];"),
+    "md_mul_drops_last_level": ("S[m - 1] = fma(x[i], y[m - 1 - i], S[m - 1]);", "(void)i;"),
+    "two_prod_no_error": ("*e = fma(a, b, -pp);", "*e = 0.0;"),
+    "two_sum_sign": ("double err = (a - (ss - bb)) + (b - bb);", "double err = (a - (ss - bb)) - (b - bb);"),
+    "renorm_skips_top_down": ("two_sum(e, u[j + 1], &r[j], &e);", "r[j] = u[j + 1];"),
+    "conv_skips_first_term": ("for (int i = 1; i <= k; ++i) {\n            md_mul(m, x + (size_t)i * m",
+                              "for (int i = 2; i <= k; ++i) {\n            md_mul(m, x + (size_t)i * m"),
+    "tree_drops_carry": ("        if (r % 2)\n            live[w++] = live[r - 1];\n        r = w;\n    }\n    free(live);\n}\n\n/* The schedule",
+                         "        r = w;\n    }\n    free(live);\n}\n\n/* The schedule"),
+    "last_partial_misassigned": ("memcpy(der[n - 1], F(n - 1), sizeof(double) * S);",
+                                 "memcpy(der[n - 1], F(n - 2), sizeof(double) * S);"),
+}
+
+
+def _pins_pass(L) -> bool:
+    """Run a battery of exact pins against library L; False as soon as one fails."""
+    cases = []
+    for m in (1, 2, 3):
+        for seed in range(1, 6):
+            rng = np.random.default_rng(77 * m + seed)
+            n = int(rng.integers(2, 7))
+            N = int(rng.integers(1, 7))
+            nk = rng.integers(1, n + 1, size=N)
+            cases.append(W.random_poly("mut", m, int(rng.integers(1, 4)), n, N, nk, seed))
+        cases.append(W.make("ex", m, 3, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4))
+        cases.append(W.make("n5", m, 2, 7, [(0, 2, 3, 5, 6)], seed=9))
+    for w in cases:
+        val, grad = O.eval_workload(w, L=L)
+        (ev, eg), (mv, mg) = E.workload_exact(w)
+        b = E.bound(w.m, w.d)
+        if E.max_scaled_error(val, ev, mv) > b:
+            return False
+        for i in range(w.n):
+            if E.max_scaled_error(grad[:, i, :], eg[i], mg[i]) > b:
+                return False
+    return True
+
+
+def test_unmutated_oracle_passes_battery(oracle_lib):
+    assert _pins_pass(O.lib())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    src = open(obuild.SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    mutant = src.replace(old, new, 1)
+    c = tmp_path / "mutant.c"
+    c.write_text(mutant)
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", *obuild.CFLAGS, str(c), "-o", str(so), "-lm"], check=True)
+    L = O.bind(str(so))
+    assert not _pins_pass(L), f"planted mistake {name} was not caught"
