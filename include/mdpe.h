@@ -1,0 +1,153 @@
+/*
+ * mdpe.h -- C ABI of libmdpe: evaluation and differentiation of a sparse
+ * polynomial at power series truncated at degree d, in m-fold double
+ * arithmetic, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: J. Verschelde, "Accelerated polynomial evaluation and
+ * differentiation at power series in multiple double precision"
+ * (arXiv 2101.10881).  The polynomial is eq. (3) of Section 4; products of
+ * series are the truncated convolutions of eq. (1), Section 2; the gradient
+ * comes from the forward / backward / cross products of Section 3, run as
+ * layers of convolution jobs followed by levels of addition jobs on one
+ * data array (Section 5, Fig. 1, eq. (6)).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (MDPE_OK) on success or a negative mdpe_status; nothing
+ *     throws.  last_error_string() gives a message for the calling thread.
+ *   - A multiple double is m consecutive limbs of binary64, limb 0 the most
+ *     significant; values are normalised expansions (|x_{j+1}| <= ulp(x_j)/2).
+ *   - User series buffers are limb-planar and row-major (the m data arrays of
+ *     Section 5): a batch of `count` series is double[m][count][d+1].
+ *   - Device buffers are owned by the caller (e.g. torch tensors); the library
+ *     allocates nothing during evaluation.  Work is enqueued on the caller's
+ *     HIP stream (hipStream_t passed as void*; NULL = default stream) and is
+ *     asynchronous: outputs are ready when that stream reaches them.
+ */
+#ifndef MDPE_H
+#define MDPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDPE_OK = 0,
+    MDPE_EINVAL = -1,       /* bad argument or polynomial description */
+    MDPE_EUNSUPPORTED = -2, /* m not in {1,2,3,4,5,8,10}, or d too large for one workgroup's LDS */
+    MDPE_ENOMEM = -3,       /* host or device allocation failed at plan time */
+    MDPE_EDEVICE = -4       /* a HIP runtime call failed (its message is kept) */
+} mdpe_status;
+
+/* Opaque plan: job lists for one polynomial structure, immutable once built,
+ * safe to share between threads. */
+typedef struct mdpe_plan mdpe_plan;
+
+/* Polynomial structure (Section 5, the input list: N, n, d, supports). */
+typedef struct {
+    int32_t n;              /* number of variables, n >= 1 */
+    int32_t N;              /* number of monomials, a_0 not counted, N >= 0 */
+    int32_t d;              /* truncation degree, d >= 0: every series has d+1 coefficients */
+    int32_t m;              /* limbs per coefficient, one of 1, 2, 3, 4, 5, 8, 10 */
+    const int32_t *nvars;   /* host [N]: n_k, 1 <= n_k <= n */
+    const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
+                               increasing inside each monomial (Section 4) */
+    uint32_t flags;         /* reserved, must be 0 */
+} mdpe_poly_desc;
+
+/* Plan summary. */
+typedef struct {
+    int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
+    int64_t n_conv;         /* convolution jobs: sum over monomials of 3 n_k - 3 (1 if n_k = 1) */
+    int64_t n_add;          /* addition jobs */
+    int32_t n_layers;       /* convolution launches = largest n_k */
+    int32_t n_levels;       /* addition launches */
+    int64_t workspace_bytes;/* device workspace eval_and_diff needs: n_series*(d+1)*m*8 */
+    int32_t jobs_per_group; /* convolution jobs per 64-lane workgroup */
+    int32_t lane_steps;     /* multiply-add steps per lane per workgroup (lane schedule length) */
+    int32_t n, N, d, m;
+} mdpe_plan_info;
+
+/*
+ * Build a plan (Section 5, the data staging algorithm): series slots
+ * a_0, a_1..a_N, z_1..z_n, then all forward, backward and cross products;
+ * the convolution triplets of every layer; the addition pairs of every
+ * level of the pairwise tree; the output slots; a hazard check (no job
+ * writes a slot another job of its layer reads or writes).
+ * device >= 0: the job arrays are uploaded to that HIP device once.
+ * device == -1: a host-only plan for inspection (eval_and_diff refuses it).
+ * desc and its arrays are only read during the call.
+ */
+int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out);
+
+int plan_info(const mdpe_plan *plan, mdpe_plan_info *out);
+
+/* conv_sizes[n_layers], add_sizes[n_levels]: jobs per launch (either may be NULL). */
+int plan_layer_sizes(const mdpe_plan *plan, int32_t *conv_sizes, int32_t *add_sizes);
+
+/* Convolution jobs as rows {layer (1-based), t1, t2, t3} in slot units (a slot
+ * is one series of d+1 coefficients; slot s starts at s*(d+1) in the paper's
+ * array A); job meaning A[t3] := A[t1] * A[t2].  rows: int32[n_conv][4], in
+ * launch order. */
+int plan_conv_jobs(const mdpe_plan *plan, int32_t *rows);
+
+/* Addition jobs as rows {level (1-based), t1, t2}: A[t2] := A[t2] + A[t1].
+ * rows: int32[n_add][3], in launch order. */
+int plan_add_jobs(const mdpe_plan *plan, int32_t *rows);
+
+/* out_slots[1+n]: slot holding the value, then for each variable the slot
+ * holding its partial derivative, or -1 when the variable is absent. */
+int plan_outputs(const mdpe_plan *plan, int32_t *out_slots);
+
+/*
+ * Evaluate p and its gradient (Sections 4-5).
+ *   coeff     device double[m][N+1][d+1], a_0 first (read only)
+ *   z         device double[m][n][d+1] (read only)
+ *   value     device double[m][d+1] (written)
+ *   grad      device double[m][n][d+1] (written; absent variables get +0.0)
+ *   workspace device buffer of plan_info().workspace_bytes, 256-byte aligned;
+ *             its contents are scratch and may be reused between calls
+ *             that are ordered on one stream
+ *   stream    hipStream_t or NULL
+ * Launches: one staging kernel, one convolution kernel per layer, one
+ * addition kernel per level, one gather kernel.  Calls on different streams
+ * must not share a workspace.
+ */
+int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
+                  double *grad, void *workspace, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream, in the
+ * paper's four categories (Section 6.2: convolution, addition, their sum; the
+ * caller measures wall time).  Times accumulate over calls until read. */
+typedef struct mdpe_profiler mdpe_profiler;
+typedef struct {
+    double stage_ms, cnv_ms, add_ms, gather_ms;
+    int64_t n_stage, n_cnv, n_add, n_gather; /* launches timed */
+} mdpe_times;
+
+int profiler_create(mdpe_profiler **out);
+/* Same as eval_and_diff, with an event pair around every launch. */
+int eval_and_diff_profiled(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
+                           double *grad, void *workspace, void *stream, mdpe_profiler *prof);
+/* Wait for the recorded events, add their durations into *out, reset. */
+int profiler_read(mdpe_profiler *prof, mdpe_times *out);
+void profiler_destroy(mdpe_profiler *prof);
+
+/*
+ * Elementwise m-double operation on device arrays (op 0: z = x + y,
+ * op 1: z = x * y), planar double[m][count].  Diagnostic entry point that
+ * exposes the device multiple-double library the kernels use.
+ */
+int md_elementwise(int op, int m, int64_t count, const double *x, const double *y, double *z, void *stream);
+
+/* Release a plan (its device job arrays).  NULL is ignored. */
+void plan_destroy(mdpe_plan *plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *last_error_string(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDPE_H */

@@ -1,0 +1,557 @@
+// kernels.hip -- HIP kernels for gfx950 and the C ABI of include/mdpe.h.
+//
+// Data layout in HBM (workspace A): slot-major, then coefficient, then limb:
+// A[slot][c][l], one slot = one series = (d+1)*M doubles, so the M limbs of a
+// coefficient are contiguous (80 bytes at M = 10) and a series is one
+// contiguous block.  User buffers are limb-planar [M][count][d+1]; the
+// staging and gather kernels convert.
+//
+// Kernels
+//   stage_kernel         user coeff / z -> input slots of A (+ n_k = 1 copies)
+//   conv_layer_kernel<M> one 64-lane workgroup stages J jobs' two input series
+//                        in LDS and computes their J*(d+1) output coefficients;
+//                        each coefficient is one lane's sequential chain
+//                        z_k = x_0 y_k, z_k += x_i y_{k-i} (i = 1..k), and the
+//                        chains are spread over the lanes by a host-made
+//                        longest-first schedule (Section 2, eq. (1); Section 5,
+//                        the convolution kernel)
+//   add_level_kernel<M>  one thread per coefficient of every pair of a level:
+//                        A[t2] := A[t2] + A[t1] (Section 5, the addition kernel)
+//   gather_kernel        output slots -> user value / gradient (zeros if absent)
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mdpe.h"
+#include "md.hpp"
+#include "plan.hpp"
+
+namespace mdpe {
+
+// ------------------------------------------------------------------ kernels
+
+template <int M>
+__global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                        int njobs, int d, int J, const int *__restrict__ chains,
+                                                        int stride, int steps) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const long S = (long)(d + 1) * M;
+    const int g0 = blockIdx.x * J;
+    const int jn = min(J, njobs - g0);
+    double *X = lds;
+    double *Y = lds + (long)J * S;
+    for (int j = 0; j < jn; ++j) {
+        const int4 t = jobs[g0 + j];
+        const double *xs = A + (long)t.x * S;
+        const double *ys = A + (long)t.y * S;
+        for (long q = lane; q < S; q += 64) {
+            X[j * S + q] = xs[q];
+            Y[j * S + q] = ys[q];
+        }
+    }
+    __syncthreads();
+
+    const int *my = chains + (long)lane * stride;
+    int c = 0;
+    int code = my[0];
+    int j = 0, k = 0, i = 0;
+    bool live = false;
+    if (code >= 0) {
+        j = code >> 16;
+        k = code & 0xffff;
+        live = j < jn;
+    }
+    double acc[M];
+    for (int s = 0; s < steps; ++s) {
+        double xv[M], yv[M], p[M];
+        const double *xp = X + j * S + i * M;
+        const double *yp = Y + j * S + (k - i) * M;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            xv[l] = xp[l];
+            yv[l] = yp[l];
+        }
+        md_mul<M>(xv, yv, p);
+        if (i == 0) {
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc[l] = p[l];
+        } else {
+            md_add<M>(acc, p, acc);
+        }
+        if (i == k) {
+            if (live) {
+                double *out = A + (long)jobs[g0 + j].z * S + (long)k * M;
+#pragma unroll
+                for (int l = 0; l < M; ++l) out[l] = acc[l];
+            }
+            if (code >= 0) code = my[++c];
+            if (code >= 0) {
+                j = code >> 16;
+                k = code & 0xffff;
+                live = j < jn;
+            } else {
+                j = 0;
+                k = 0;
+                live = false;
+            }
+            i = 0;
+        } else {
+            ++i;
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void add_level_kernel(double *__restrict__ A, const int2 *__restrict__ pairs,
+                                                        long total, int d) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int d1 = d + 1;
+    const long p = idx / d1;
+    const int c = (int)(idx - p * d1);
+    const int2 t = pairs[p];
+    const long S = (long)d1 * M;
+    double *up = A + (long)t.y * S + (long)c * M;
+    const double *in = A + (long)t.x * S + (long)c * M;
+    double x[M], y[M], z[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        x[l] = up[l];
+        y[l] = in[l];
+    }
+    md_add<M>(x, y, z);
+#pragma unroll
+    for (int l = 0; l < M; ++l) up[l] = z[l];
+}
+
+__global__ __launch_bounds__(256) void stage_kernel(double *__restrict__ A, const double *__restrict__ coeff,
+                                                    const double *__restrict__ z, const int2 *__restrict__ entries,
+                                                    long total, int N, int n, int d, int m) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int d1 = d + 1;
+    const long e = idx / d1;
+    const int c = (int)(idx - e * d1);
+    const int2 en = entries[e];
+    double *dst = A + (long)en.x * d1 * m + (long)c * m;
+    if (en.y <= N) {
+        for (int l = 0; l < m; ++l) dst[l] = coeff[((long)l * (N + 1) + en.y) * d1 + c];
+    } else {
+        const int i = en.y - N - 1;
+        for (int l = 0; l < m; ++l) dst[l] = z[((long)l * n + i) * d1 + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ A, double *__restrict__ value,
+                                                     double *__restrict__ grad, const int *__restrict__ out_slots,
+                                                     int n, int d, int m) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const int d1 = d + 1;
+    if (idx >= (long)(1 + n) * d1) return;
+    const int o = (int)(idx / d1);
+    const int c = (int)(idx - (long)o * d1);
+    const int slot = out_slots[o];
+    for (int l = 0; l < m; ++l) {
+        const double v = slot >= 0 ? A[(long)slot * d1 * m + (long)c * m + l] : 0.0;
+        if (o == 0)
+            value[(long)l * d1 + c] = v;
+        else
+            grad[((long)l * n + (o - 1)) * d1 + c] = v;
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void md_elementwise_kernel(int op, long count, const double *__restrict__ x,
+                                                             const double *__restrict__ y, double *__restrict__ z) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    double a[M], b[M], r[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        a[l] = x[(long)l * count + i];
+        b[l] = y[(long)l * count + i];
+    }
+    if (op == 0)
+        md_add<M>(a, b, r);
+    else
+        md_mul<M>(a, b, r);
+#pragma unroll
+    for (int l = 0; l < M; ++l) z[(long)l * count + i] = r[l];
+}
+
+}  // namespace mdpe
+
+// ------------------------------------------------------------------ runtime
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(MDPE_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct mdpe_plan {
+    mdpe::Plan P;
+    int device = -1;
+    int4 *d_conv = nullptr;
+    int2 *d_add = nullptr;
+    int2 *d_stage = nullptr;
+    int *d_out = nullptr;
+    int *d_chains = nullptr;
+};
+
+struct mdpe_profiler {
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    size_t used = 0;
+};
+
+namespace {
+
+void free_plan(mdpe_plan *p) {
+    if (!p) return;
+    if (p->device >= 0) {
+        DeviceGuard g(p->device);
+        (void)hipFree(p->d_conv);
+        (void)hipFree(p->d_add);
+        (void)hipFree(p->d_stage);
+        (void)hipFree(p->d_out);
+        (void)hipFree(p->d_chains);
+    }
+    delete p;
+}
+
+template <class T>
+int upload(T **dst, const void *src, size_t bytes) {
+    if (bytes == 0) bytes = sizeof(T);
+    HIP_TRY(hipMalloc((void **)dst, bytes));
+    if (src) HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return MDPE_OK;
+}
+
+int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
+    if (!prof) return MDPE_OK;
+    if (start) {
+        if (prof->used == prof->recs.size()) {
+            mdpe_profiler::Rec r{cls, nullptr, nullptr};
+            HIP_TRY(hipEventCreate(&r.a));
+            HIP_TRY(hipEventCreate(&r.b));
+            prof->recs.push_back(r);
+        }
+        prof->recs[prof->used].cls = cls;
+        HIP_TRY(hipEventRecord(prof->recs[prof->used].a, st));
+    } else {
+        HIP_TRY(hipEventRecord(prof->recs[prof->used].b, st));
+        prof->used++;
+    }
+    return MDPE_OK;
+}
+
+#define LAUNCH_CHECK(what)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess) return fail(MDPE_EDEVICE, std::string(what ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <int M>
+int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    const int J = P.lanes.jobs_per_group;
+    const size_t lds = (size_t)2 * J * (P.d + 1) * M * sizeof(double);
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        attr_set = true;
+    }
+    for (int L = 1; L <= P.n_layers(); ++L) {
+        const long off = P.conv_off[L - 1];
+        const int nj = (int)(P.conv_off[L] - off);
+        if (nj == 0) continue;
+        const int groups = (nj + J - 1) / J;
+        int rc = record(prof, 1, st, true);
+        if (rc) return rc;
+        hipLaunchKernelGGL(mdpe::conv_layer_kernel<M>, dim3(groups), dim3(64), lds, st, A, pl->d_conv + off, nj, P.d,
+                           J, pl->d_chains, P.lanes.stride, P.lanes.steps);
+        LAUNCH_CHECK("conv_layer_kernel");
+        if ((rc = record(prof, 1, st, false))) return rc;
+    }
+    return MDPE_OK;
+}
+
+template <int M>
+int launch_add(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    for (int r = 1; r <= P.n_levels(); ++r) {
+        const long off = P.add_off[r - 1];
+        const long np = P.add_off[r] - off;
+        if (np == 0) continue;
+        const long total = np * (P.d + 1);
+        int rc = record(prof, 2, st, true);
+        if (rc) return rc;
+        hipLaunchKernelGGL(mdpe::add_level_kernel<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A,
+                           pl->d_add + off, total, P.d);
+        LAUNCH_CHECK("add_level_kernel");
+        if ((rc = record(prof, 2, st, false))) return rc;
+    }
+    return MDPE_OK;
+}
+
+template <int M>
+int run_md(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    int rc = launch_conv<M>(pl, A, st, prof);
+    if (rc) return rc;
+    return launch_add<M>(pl, A, st, prof);
+}
+
+int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
+              void *workspace, void *stream, mdpe_profiler *prof) {
+    if (!pl) return fail(MDPE_EINVAL, "plan is NULL");
+    if (pl->device < 0) return fail(MDPE_EINVAL, "host-only plan (device -1) cannot evaluate");
+    const mdpe::Plan &P = pl->P;
+    if (!coeff || !z || !value || !grad || !workspace)
+        return fail(MDPE_EINVAL, "NULL buffer (coeff, z, value, grad and workspace are required)");
+    if (((uintptr_t)workspace) % 256) return fail(MDPE_EINVAL, "workspace must be 256-byte aligned");
+    DeviceGuard g(pl->device);
+    if (!g.ok) return fail(MDPE_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    double *A = (double *)workspace;
+    const int d1 = P.d + 1;
+    int rc;
+    {
+        const long total = (long)P.stage.size() * d1;
+        if ((rc = record(prof, 0, st, true))) return rc;
+        hipLaunchKernelGGL(mdpe::stage_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, coeff, z,
+                           pl->d_stage, total, P.N, P.n, P.d, P.m);
+        LAUNCH_CHECK("stage_kernel");
+        if ((rc = record(prof, 0, st, false))) return rc;
+    }
+    switch (P.m) {
+        case 1: rc = run_md<1>(pl, A, st, prof); break;
+        case 2: rc = run_md<2>(pl, A, st, prof); break;
+        case 3: rc = run_md<3>(pl, A, st, prof); break;
+        case 4: rc = run_md<4>(pl, A, st, prof); break;
+        case 5: rc = run_md<5>(pl, A, st, prof); break;
+        case 8: rc = run_md<8>(pl, A, st, prof); break;
+        case 10: rc = run_md<10>(pl, A, st, prof); break;
+        default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
+    }
+    if (rc) return rc;
+    {
+        const long total = (long)(1 + P.n) * d1;
+        if ((rc = record(prof, 3, st, true))) return rc;
+        hipLaunchKernelGGL(mdpe::gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, value,
+                           grad, pl->d_out, P.n, P.d, P.m);
+        LAUNCH_CHECK("gather_kernel");
+        if ((rc = record(prof, 3, st, false))) return rc;
+    }
+    return MDPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
+    if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
+    *out = nullptr;
+    if (desc->flags != 0) return fail(MDPE_EINVAL, "flags must be 0");
+    if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
+    std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
+    if (!pl) return fail(MDPE_ENOMEM, "host allocation failed");
+    bool unsupported = false;
+    std::string err;
+    try {
+        err = mdpe::build_plan(desc->n, desc->N, desc->d, desc->m, desc->nvars, desc->vars, pl->P, &unsupported);
+    } catch (const std::bad_alloc &) {
+        return fail(MDPE_ENOMEM, "host allocation failed while planning");
+    }
+    if (!err.empty()) return fail(unsupported ? MDPE_EUNSUPPORTED : MDPE_EINVAL, err);
+    if (device >= 0) {
+        int ndev = 0;
+        HIP_TRY(hipGetDeviceCount(&ndev));
+        if (device >= ndev) return fail(MDPE_EINVAL, "no such device");
+        DeviceGuard g(device);
+        if (!g.ok) return fail(MDPE_EDEVICE, "cannot select device");
+        pl->device = device;
+        const mdpe::Plan &P = pl->P;
+        std::vector<int4> conv(P.conv.size());
+        for (size_t q = 0; q < P.conv.size(); ++q) conv[q] = make_int4(P.conv[q][0], P.conv[q][1], P.conv[q][2], 0);
+        std::vector<int2> add(P.add.size()), stage(P.stage.size());
+        for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
+        for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
+        int rc;
+        mdpe_plan *raw = pl.get();
+        if ((rc = upload(&raw->d_conv, conv.data(), conv.size() * sizeof(int4))) ||
+            (rc = upload(&raw->d_add, add.data(), add.size() * sizeof(int2))) ||
+            (rc = upload(&raw->d_stage, stage.data(), stage.size() * sizeof(int2))) ||
+            (rc = upload(&raw->d_out, P.out_slots.data(), P.out_slots.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_chains, P.lanes.chains.data(), P.lanes.chains.size() * sizeof(int)))) {
+            std::string keep = g_err;
+            free_plan(pl.release());
+            g_err = keep;
+            return rc;
+        }
+    }
+    *out = pl.release();
+    return MDPE_OK;
+}
+
+int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
+    if (!pl || !o) return fail(MDPE_EINVAL, "plan and out are required");
+    const mdpe::Plan &P = pl->P;
+    o->n_series = P.n_series;
+    o->n_conv = (int64_t)P.conv.size();
+    o->n_add = (int64_t)P.add.size();
+    o->n_layers = P.n_layers();
+    o->n_levels = P.n_levels();
+    o->workspace_bytes = P.n_series * (int64_t)(P.d + 1) * P.m * (int64_t)sizeof(double);
+    o->jobs_per_group = P.lanes.jobs_per_group;
+    o->lane_steps = P.lanes.steps;
+    o->n = P.n;
+    o->N = P.N;
+    o->d = P.d;
+    o->m = P.m;
+    return MDPE_OK;
+}
+
+int plan_layer_sizes(const mdpe_plan *pl, int32_t *conv_sizes, int32_t *add_sizes) {
+    if (!pl) return fail(MDPE_EINVAL, "plan is NULL");
+    const mdpe::Plan &P = pl->P;
+    if (conv_sizes)
+        for (int L = 0; L < P.n_layers(); ++L) conv_sizes[L] = (int32_t)(P.conv_off[L + 1] - P.conv_off[L]);
+    if (add_sizes)
+        for (int r = 0; r < P.n_levels(); ++r) add_sizes[r] = (int32_t)(P.add_off[r + 1] - P.add_off[r]);
+    return MDPE_OK;
+}
+
+int plan_conv_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    for (int L = 1; L <= P.n_layers(); ++L)
+        for (int64_t q = P.conv_off[L - 1]; q < P.conv_off[L]; ++q) {
+            rows[4 * q] = L;
+            rows[4 * q + 1] = P.conv[q][0];
+            rows[4 * q + 2] = P.conv[q][1];
+            rows[4 * q + 3] = P.conv[q][2];
+        }
+    return MDPE_OK;
+}
+
+int plan_add_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    for (int r = 1; r <= P.n_levels(); ++r)
+        for (int64_t q = P.add_off[r - 1]; q < P.add_off[r]; ++q) {
+            rows[3 * q] = r;
+            rows[3 * q + 1] = P.add[q][0];
+            rows[3 * q + 2] = P.add[q][1];
+        }
+    return MDPE_OK;
+}
+
+int plan_outputs(const mdpe_plan *pl, int32_t *out_slots) {
+    if (!pl || !out_slots) return fail(MDPE_EINVAL, "plan and out_slots are required");
+    std::memcpy(out_slots, pl->P.out_slots.data(), pl->P.out_slots.size() * sizeof(int32_t));
+    return MDPE_OK;
+}
+
+int eval_and_diff(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
+                  void *workspace, void *stream) {
+    return eval_impl(pl, coeff, z, value, grad, workspace, stream, nullptr);
+}
+
+int eval_and_diff_profiled(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
+                           void *workspace, void *stream, mdpe_profiler *prof) {
+    if (!prof) return fail(MDPE_EINVAL, "profiler is NULL");
+    return eval_impl(pl, coeff, z, value, grad, workspace, stream, prof);
+}
+
+int profiler_create(mdpe_profiler **out) {
+    if (!out) return fail(MDPE_EINVAL, "out is NULL");
+    *out = new (std::nothrow) mdpe_profiler();
+    return *out ? MDPE_OK : fail(MDPE_ENOMEM, "host allocation failed");
+}
+
+int profiler_read(mdpe_profiler *prof, mdpe_times *o) {
+    if (!prof || !o) return fail(MDPE_EINVAL, "profiler and out are required");
+    for (size_t q = 0; q < prof->used; ++q) {
+        auto &r = prof->recs[q];
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        switch (r.cls) {
+            case 0: o->stage_ms += ms; o->n_stage++; break;
+            case 1: o->cnv_ms += ms; o->n_cnv++; break;
+            case 2: o->add_ms += ms; o->n_add++; break;
+            default: o->gather_ms += ms; o->n_gather++; break;
+        }
+    }
+    prof->used = 0;
+    return MDPE_OK;
+}
+
+void profiler_destroy(mdpe_profiler *prof) {
+    if (!prof) return;
+    for (auto &r : prof->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    delete prof;
+}
+
+int md_elementwise(int op, int m, int64_t count, const double *x, const double *y, double *z, void *stream) {
+    if (op < 0 || op > 1) return fail(MDPE_EINVAL, "op must be 0 (add) or 1 (mul)");
+    if (count < 0) return fail(MDPE_EINVAL, "count < 0");
+    if (count == 0) return MDPE_OK;
+    if (!x || !y || !z) return fail(MDPE_EINVAL, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)((count + 255) / 256));
+    switch (m) {
+        case 1: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<1>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 2: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<2>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 3: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<3>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 4: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<4>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 5: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<5>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 8: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<8>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 10: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<10>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
+    }
+    LAUNCH_CHECK("md_elementwise_kernel");
+    return MDPE_OK;
+}
+
+void plan_destroy(mdpe_plan *pl) { free_plan(pl); }
+
+const char *last_error_string(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+// plan.cpp -- the data staging algorithm of Section 5 of the paper.
+//
+// Slots (one slot = one series of d+1 coefficients; slot s starts at
+// s*(d+1) in the paper's array A, Fig. 1):
+//   a_0 = 0, a_k = k (k = 1..N), z_i = N + i (i = 1..n),
+//   f_{k,j} = 1+N+n + alpha_k + j-1,
+//   b_{k,j} = 1+N+n + alpha_{N+1} + beta_k + j-1,
+//   c_{k,j} = 1+N+n + alpha_{N+1} + beta_{N+1} + gamma_k + j-1,
+// with alpha, beta, gamma the prefix sums of n_l, max(1, n_l-2), max(0, n_l-2)
+// (Section 5; the slot count is e/(d+1) of eq. (6)).
+//
+// Convolution jobs per monomial (Section 3, statement list and eq. (2);
+// Section 5, steps 1-7) with the readings: forward chain by z_{i_j};
+// c_j = f_j * b_{n-2-j} at layer max(j, n-2-j)+1; b_{n-2} := b_{n-2} * a and
+// c_{n-2} = f_{n-2} * z_{i_n} at layer n-1; n = 2: b_1 = z_{i_2} * a; n = 1:
+// the derivative is a_k itself, copied into its b slot at staging time.
+//
+// Addition jobs: per output list a pairwise tree, adjacent pairs with the odd
+// element carried, the later element updated (Section 5, the addition
+// recursion, read through the worked example after eq. (5)).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <numeric>
+#include <unordered_map>
+
+namespace mdpe {
+
+static bool supported_m(int m) { return m == 1 || m == 2 || m == 3 || m == 4 || m == 5 || m == 8 || m == 10; }
+
+int choose_jobs_per_group(int d, int m) {
+    // Enough jobs per wavefront that the average lane load, J(d+1)(d+2)/2/64,
+    // covers the longest output coefficient (d+1 multiply-adds); within the
+    // LDS budget.
+    int need = (2 * kLanes + (d + 2) - 1) / (d + 2);
+    need = std::max(1, std::min(need, kLanes));
+    long per_job = 2L * (d + 1) * m * 8;
+    long cap = std::max(1L, (long)kLdsBudget / per_job);
+    return (int)std::max(1L, std::min((long)need, cap));
+}
+
+LaneSchedule make_lane_schedule(int d, int J) {
+    // Assign the J*(d+1) output coefficients (coefficient k costs k+1
+    // multiply-adds) to 64 lanes: first-fit-decreasing into lanes of capacity
+    // C, for the smallest C >= max(ceil(total/64), d+1) that fits.  Each
+    // coefficient stays whole on one lane, so its operation order is the
+    // specified one whatever lane computes it.
+    LaneSchedule s;
+    s.jobs_per_group = J;
+    std::vector<std::pair<int, int>> items;  // (length, code)
+    long total = 0;
+    for (int j = 0; j < J; ++j)
+        for (int k = 0; k <= d; ++k) {
+            items.push_back({k + 1, (j << 16) | k});
+            total += k + 1;
+        }
+    std::stable_sort(items.begin(), items.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    std::vector<long> load;
+    std::vector<std::vector<int32_t>> lists;
+    for (long cap = std::max((total + kLanes - 1) / kLanes, (long)d + 1);; ++cap) {
+        load.assign(kLanes, 0);
+        lists.assign(kLanes, {});
+        bool ok = true;
+        for (auto &it : items) {
+            int l = 0;
+            while (l < kLanes && load[l] + it.first > cap) ++l;
+            if (l == kLanes) {
+                ok = false;
+                break;
+            }
+            load[l] += it.first;
+            lists[l].push_back(it.second);
+        }
+        if (ok) break;
+    }
+    size_t stride = 1;
+    for (auto &l : lists) stride = std::max(stride, l.size() + 1);
+    s.stride = (int)stride;
+    s.steps = (int)*std::max_element(load.begin(), load.end());
+    s.chains.assign((size_t)kLanes * stride, -1);
+    for (int l = 0; l < kLanes; ++l)
+        for (size_t q = 0; q < lists[l].size(); ++q) s.chains[(size_t)l * stride + q] = lists[l][q];
+    return s;
+}
+
+// Pairwise tree over `items`; pushes the jobs of round r into rounds[r].
+static int tree_rounds(std::vector<int32_t> live, std::vector<std::vector<std::array<int32_t, 2>>> &rounds) {
+    int r = 0;
+    while (live.size() > 1) {
+        if ((int)rounds.size() <= r) rounds.emplace_back();
+        std::vector<int32_t> next;
+        size_t pairs = live.size() / 2;
+        for (size_t p = 0; p < pairs; ++p) {
+            rounds[r].push_back({live[2 * p], live[2 * p + 1]});
+            next.push_back(live[2 * p + 1]);
+        }
+        if (live.size() % 2) next.push_back(live.back());
+        live.swap(next);
+        ++r;
+    }
+    return live.empty() ? -1 : live[0];
+}
+
+static std::string check_hazards(const Plan &P) {
+    // Each slot's last writer stage: inputs at stage 0, conv layer L at stage
+    // L, addition level r at stage n_layers + r.  A job may read a slot only
+    // when it was written at an earlier stage, and two jobs of one stage may
+    // not touch a slot that one of them writes.
+    std::vector<int> written(P.n_series, -1);
+    for (int s = 0; s < 1 + P.N + P.n; ++s) written[s] = 0;
+    for (auto &c : P.stage) written[c[0]] = 0;
+    auto stage_check = [&](int stage, const std::vector<std::array<int32_t, 3>> &jobs) -> std::string {
+        std::unordered_map<int32_t, int> writer;
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            int32_t w = jobs[q][2];
+            if (w < 0 || w >= P.n_series) return "slot out of range";
+            if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
+        }
+        for (size_t q = 0; q < jobs.size(); ++q)
+            for (int r = 0; r < 2; ++r) {
+                int32_t s = jobs[q][r];
+                if (s < 0 || s >= P.n_series) return "slot out of range";
+                if (written[s] < 0 || written[s] >= stage) return "read before write";
+                auto it = writer.find(s);
+                if (it != writer.end() && it->second != (int)q) return "read of a slot written in the same stage";
+            }
+        for (auto &j : jobs) written[j[2]] = stage;
+        return "";
+    };
+    for (int L = 1; L <= P.n_layers(); ++L) {
+        std::vector<std::array<int32_t, 3>> jobs(P.conv.begin() + P.conv_off[L - 1], P.conv.begin() + P.conv_off[L]);
+        auto e = stage_check(L, jobs);
+        if (!e.empty()) return "conv layer " + std::to_string(L) + ": " + e;
+    }
+    for (int r = 1; r <= P.n_levels(); ++r) {
+        std::vector<std::array<int32_t, 3>> jobs;
+        for (int64_t q = P.add_off[r - 1]; q < P.add_off[r]; ++q) jobs.push_back({P.add[q][0], P.add[q][1], P.add[q][1]});
+        auto e = stage_check(P.n_layers() + r, jobs);
+        if (!e.empty()) return "add level " + std::to_string(r) + ": " + e;
+    }
+    for (auto s : P.out_slots)
+        if (s >= 0 && written[s] < 0) return "output slot never written";
+    return "";
+}
+
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, Plan &P,
+                       bool *unsupported) {
+    *unsupported = false;
+    if (n < 1 || N < 0 || d < 0) return "need n >= 1, N >= 0, d >= 0";
+    if (!supported_m(m)) {
+        *unsupported = true;
+        return "m must be one of 1, 2, 3, 4, 5, 8, 10";
+    }
+    if (N > 0 && (!nvars || !vars)) return "nvars/vars missing";
+    int64_t tot = 0, nb = 0, nc = 0;
+    int nmax = 0;
+    for (int k = 0; k < N; ++k) {
+        int nk = nvars[k];
+        if (nk < 1 || nk > n) return "monomial " + std::to_string(k) + ": n_k out of range";
+        for (int j = 0; j < nk; ++j) {
+            int v = vars[tot + j];
+            if (v < 0 || v >= n) return "monomial " + std::to_string(k) + ": variable out of range";
+            if (j > 0 && v <= vars[tot + j - 1]) return "monomial " + std::to_string(k) + ": variables not strictly increasing";
+        }
+        tot += nk;
+        nb += std::max(1, nk - 2);
+        nc += std::max(0, nk - 2);
+        nmax = std::max(nmax, nk);
+    }
+    const int64_t base = 1 + (int64_t)N + n;
+    const int64_t nser = base + tot + nb + nc;
+    if (nser > INT32_MAX / 2) {
+        *unsupported = true;
+        return "too many series for 32-bit slot indices";
+    }
+    if (2L * (d + 1) * m * 8 > kMaxLdsBytes) {
+        *unsupported = true;
+        return "d too large: one convolution job must fit in one workgroup's LDS (2(d+1)m*8 <= 163840 bytes)";
+    }
+    if (d + 1 > 65535) {
+        *unsupported = true;
+        return "d too large";
+    }
+    P = Plan();
+    P.n = n;
+    P.N = N;
+    P.d = d;
+    P.m = m;
+    P.n_series = nser;
+
+    std::vector<std::vector<std::array<int32_t, 3>>> layers(std::max(nmax, 1));
+    std::vector<int32_t> value_list{0};
+    std::vector<std::vector<int32_t>> grad_lists(n);
+    for (int s = 0; s < 1 + N + n; ++s) P.stage.push_back({s, s});
+
+    int64_t alpha = 0, beta = 0, gamma = 0, pos = 0;
+    for (int k = 0; k < N; ++k) {
+        const int nk = nvars[k];
+        const int32_t *v = vars + pos;
+        auto A = [&](void) { return (int32_t)(k + 1); };
+        auto Z = [&](int i) { return (int32_t)(1 + N + v[i - 1]); };  // z_{i_i}, 1-based position
+        auto F = [&](int j) { return (int32_t)(base + alpha + j - 1); };
+        auto B = [&](int j) { return (int32_t)(base + tot + beta + j - 1); };
+        auto C = [&](int j) { return (int32_t)(base + tot + nb + gamma + j - 1); };
+        auto job = [&](int layer, int32_t t1, int32_t t2, int32_t t3) { layers[layer - 1].push_back({t1, t2, t3}); };
+        if (nk == 1) {
+            job(1, A(), Z(1), F(1));
+            P.stage.push_back({B(1), (int32_t)(k + 1)});
+            value_list.push_back(F(1));
+            grad_lists[v[0]].push_back(B(1));
+        } else {
+            job(1, A(), Z(1), F(1));
+            for (int j = 2; j <= nk; ++j) job(j, F(j - 1), Z(j), F(j));
+            if (nk == 2) {
+                job(1, Z(2), A(), B(1));
+                grad_lists[v[0]].push_back(B(1));
+                grad_lists[v[1]].push_back(F(1));
+            } else {
+                job(1, Z(nk), Z(nk - 1), B(1));
+                for (int j = 2; j <= nk - 2; ++j) job(j, B(j - 1), Z(nk - j), B(j));
+                job(nk - 1, B(nk - 2), A(), B(nk - 2));
+                for (int j = 1; j <= nk - 3; ++j) job(std::max(j, nk - 2 - j) + 1, F(j), B(nk - 2 - j), C(j));
+                job(nk - 1, F(nk - 2), Z(nk), C(nk - 2));
+                grad_lists[v[0]].push_back(B(nk - 2));
+                for (int j = 1; j <= nk - 2; ++j) grad_lists[v[j]].push_back(C(j));
+                grad_lists[v[nk - 1]].push_back(F(nk - 1));
+            }
+            value_list.push_back(F(nk));
+        }
+        alpha += nk;
+        beta += std::max(1, nk - 2);
+        gamma += std::max(0, nk - 2);
+        pos += nk;
+    }
+
+    P.conv_off.push_back(0);
+    if (N > 0)
+        for (auto &L : layers) {
+            P.conv.insert(P.conv.end(), L.begin(), L.end());
+            P.conv_off.push_back((int64_t)P.conv.size());
+        }
+
+    std::vector<std::vector<std::array<int32_t, 2>>> rounds;
+    P.out_slots.push_back(tree_rounds(value_list, rounds));
+    for (int i = 0; i < n; ++i) P.out_slots.push_back(tree_rounds(grad_lists[i], rounds));
+    P.add_off.push_back(0);
+    for (auto &r : rounds) {
+        P.add.insert(P.add.end(), r.begin(), r.end());
+        P.add_off.push_back((int64_t)P.add.size());
+    }
+
+    auto err = check_hazards(P);
+    if (!err.empty()) return "internal planner error: " + err;
+
+    P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, m));
+    return "";
+}
+
+}  // namespace mdpe

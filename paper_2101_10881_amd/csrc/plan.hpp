@@ -1,0 +1,53 @@
+// plan.hpp -- host-side data staging (Section 5 of the paper): series slots,
+// convolution triplets per layer, addition pairs per level, output slots,
+// hazard check and the lane schedule of the convolution kernel.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mdpe {
+
+constexpr int kLanes = 64;             // one wavefront per convolution workgroup
+constexpr int kMaxLdsBytes = 163840;   // LDS one gfx950 workgroup may allocate
+constexpr int kLdsBudget = 65536;      // LDS a workgroup aims to stay under (>= 2 per CU)
+
+struct LaneSchedule {
+    int jobs_per_group = 1;            // J: convolution jobs staged per workgroup
+    int steps = 0;                     // multiply-add steps of the busiest lane
+    int stride = 0;                    // entries per lane in `chains`
+    // chains[lane*stride + s]: (job << 16) | k for the s-th output coefficient
+    // the lane computes, -1 after its last one.
+    std::vector<int32_t> chains;
+};
+
+struct Plan {
+    int n = 0, N = 0, d = 0, m = 0;
+    int64_t n_series = 0;
+    // convolution jobs {t1, t2, t3} in launch order; layer L spans
+    // conv[conv_off[L-1] .. conv_off[L])
+    std::vector<std::array<int32_t, 3>> conv;
+    std::vector<int64_t> conv_off;
+    // addition jobs {t1, t2}: A[t2] += A[t1]; level r spans add[add_off[r-1] .. add_off[r])
+    std::vector<std::array<int32_t, 2>> add;
+    std::vector<int64_t> add_off;
+    std::vector<int32_t> out_slots;    // [1+n]: value slot, then d/dz_i slot or -1
+    // staging copies {slot, source}: source s < N+1 is coeff series s, else z series s-N-1
+    std::vector<std::array<int32_t, 2>> stage;
+    LaneSchedule lanes;
+
+    int n_layers() const { return (int)conv_off.size() - 1; }
+    int n_levels() const { return (int)add_off.size() - 1; }
+};
+
+// Returns "" on success, else a message; *unsupported distinguishes limits
+// of this implementation from invalid input.
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, Plan &out,
+                       bool *unsupported);
+
+LaneSchedule make_lane_schedule(int d, int jobs_per_group);
+int choose_jobs_per_group(int d, int m);
+
+}  // namespace mdpe

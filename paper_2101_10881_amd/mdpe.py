@@ -1,0 +1,254 @@
+"""ctypes binding of libmdpe (include/mdpe.h), same entry-point names.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of libmdpe.so.  There is no CPU fallback; loading fails loudly when
+the library has not been built.
+
+Device buffers are torch tensors (float64, contiguous, on the plan's
+device); streams are torch.cuda streams (the current one by default).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdpe.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdpe.h")
+
+MDPE_OK, MDPE_EINVAL, MDPE_EUNSUPPORTED, MDPE_ENOMEM, MDPE_EDEVICE = 0, -1, -2, -3, -4
+SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
+
+
+class MdpeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mdpe error {code}: {msg}")
+        self.code = code
+
+
+class PolyDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("nvars", ctypes.POINTER(ctypes.c_int32)), ("vars", ctypes.POINTER(ctypes.c_int32)),
+                ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_series", ctypes.c_int64), ("n_conv", ctypes.c_int64), ("n_add", ctypes.c_int64),
+                ("n_layers", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("jobs_per_group", ctypes.c_int32), ("lane_steps", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Times(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_double), ("cnv_ms", ctypes.c_double), ("add_ms", ctypes.c_double),
+                ("gather_ms", ctypes.c_double), ("n_stage", ctypes.c_int64), ("n_cnv", ctypes.c_int64),
+                ("n_add", ctypes.c_int64), ("n_gather", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_L = None
+
+
+def lib():
+    """Load libmdpe.so; raise if it is missing (no fallback)."""
+    global _L
+    if _L is not None:
+        return _L
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    L.plan_polynomial.argtypes = [ctypes.POINTER(PolyDesc), ctypes.c_int, ctypes.POINTER(_vp)]
+    L.plan_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
+    L.plan_layer_sizes.argtypes = [_vp, _i32p, _i32p]
+    L.plan_conv_jobs.argtypes = [_vp, _i32p]
+    L.plan_add_jobs.argtypes = [_vp, _i32p]
+    L.plan_outputs.argtypes = [_vp, _i32p]
+    L.eval_and_diff.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.eval_and_diff_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.profiler_create.argtypes = [ctypes.POINTER(_vp)]
+    L.profiler_read.argtypes = [_vp, ctypes.POINTER(Times)]
+    L.profiler_destroy.argtypes = [_vp]
+    L.profiler_destroy.restype = None
+    L.md_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp]
+    L.plan_destroy.argtypes = [_vp]
+    L.plan_destroy.restype = None
+    L.last_error_string.argtypes = []
+    L.last_error_string.restype = ctypes.c_char_p
+    _L = L
+    return L
+
+
+def header_symbols(path: str = HEADER):
+    """Function names declared in include/mdpe.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def _check(rc):
+    if rc != MDPE_OK:
+        raise MdpeError(rc, lib().last_error_string().decode())
+    return rc
+
+
+def last_error_string() -> str:
+    return lib().last_error_string().decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+class Plan:
+    """A plan (plan_polynomial); device -1 builds a host-only plan for inspection."""
+
+    def __init__(self, n, nvars, vars_, d, m, device=0):
+        self.nvars = np.ascontiguousarray(nvars, dtype=np.int32)
+        self.vars = np.ascontiguousarray(vars_, dtype=np.int32)
+        desc = PolyDesc(int(n), int(self.nvars.shape[0]), int(d), int(m),
+                        self.nvars.ctypes.data_as(_i32p), self.vars.ctypes.data_as(_i32p), 0)
+        h = _vp()
+        _check(lib().plan_polynomial(ctypes.byref(desc), int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        info = PlanInfo()
+        _check(lib().plan_info(h, ctypes.byref(info)))
+        self.info = info.as_dict()
+
+    @classmethod
+    def for_workload(cls, w, device=0):
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _L is not None:
+            _L.plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def layer_sizes(self):
+        conv = np.zeros(max(self.info["n_layers"], 1), dtype=np.int32)
+        add = np.zeros(max(self.info["n_levels"], 1), dtype=np.int32)
+        _check(lib().plan_layer_sizes(self._h, conv.ctypes.data_as(_i32p), add.ctypes.data_as(_i32p)))
+        return list(conv[: self.info["n_layers"]]), list(add[: self.info["n_levels"]])
+
+    def conv_jobs(self):
+        rows = np.zeros((max(self.info["n_conv"], 1), 4), dtype=np.int32)
+        _check(lib().plan_conv_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[: self.info["n_conv"]]
+
+    def add_jobs(self):
+        rows = np.zeros((max(self.info["n_add"], 1), 3), dtype=np.int32)
+        _check(lib().plan_add_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[: self.info["n_add"]]
+
+    def outputs(self):
+        out = np.zeros(1 + self.info["n"], dtype=np.int32)
+        _check(lib().plan_outputs(self._h, out.ctypes.data_as(_i32p)))
+        return out
+
+
+def plan_polynomial(n, nvars, vars_, d, m, device=0) -> Plan:
+    return Plan(n, nvars, vars_, d, m, device)
+
+
+def eval_and_diff(plan: Plan, coeff, z, value, grad, workspace, stream=None):
+    """Enqueue one evaluation on `stream` (tensors on the plan's device)."""
+    _check(lib().eval_and_diff(plan.handle, _ptr(coeff), _ptr(z), _ptr(value), _ptr(grad), _ptr(workspace),
+                               _stream(stream)))
+
+
+class Profiler:
+    def __init__(self):
+        h = _vp()
+        _check(lib().profiler_create(ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _L is not None:
+            _L.profiler_destroy(h)
+            self._h = None
+
+    def read(self) -> dict:
+        t = Times()
+        _check(lib().profiler_read(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+
+def eval_and_diff_profiled(plan: Plan, coeff, z, value, grad, workspace, prof: Profiler, stream=None):
+    _check(lib().eval_and_diff_profiled(plan.handle, _ptr(coeff), _ptr(z), _ptr(value), _ptr(grad),
+                                        _ptr(workspace), _stream(stream), prof._h))
+
+
+def md_elementwise(op, x, y, z, stream=None):
+    """z = x op y on planar [m][count] float64 device tensors; op 'add' or 'mul'."""
+    m, count = x.shape
+    _check(lib().md_elementwise({"add": 0, "mul": 1}[op], int(m), int(count), _ptr(x), _ptr(y), _ptr(z),
+                                _stream(stream)))
+
+
+class Polynomial:
+    """Plan + workspace + output buffers on one device: the convenience API.
+
+    >>> P = Polynomial(n, nvars, vars, d, m)
+    >>> value, grad = P.eval_and_diff(coeff, z)   # float64 tensors [m][N+1][d+1], [m][n][d+1]
+    """
+
+    def __init__(self, n, nvars, vars_, d, m, device=None):
+        import torch
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0)
+        self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
+        nbytes = int(self.plan.info["workspace_bytes"])
+        # 256-byte aligned by the caching allocator
+        self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
+
+    @classmethod
+    def for_workload(cls, w, device=None):
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device)
+
+    def _check_inputs(self, coeff, z):
+        import torch
+        for name, t, shape in (("coeff", coeff, (self.m, self.N + 1, self.d + 1)),
+                               ("z", z, (self.m, self.n, self.d + 1))):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
+                raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
+
+    def eval_and_diff(self, coeff, z, value=None, grad=None, stream=None, profiler=None):
+        import torch
+        self._check_inputs(coeff, z)
+        if value is None:
+            value = torch.empty((self.m, self.d + 1), dtype=torch.float64, device=self.device)
+        if grad is None:
+            grad = torch.empty((self.m, self.n, self.d + 1), dtype=torch.float64, device=self.device)
+        if profiler is None:
+            eval_and_diff(self.plan, coeff, z, value, grad, self.workspace, stream)
+        else:
+            eval_and_diff_profiled(self.plan, coeff, z, value, grad, self.workspace, profiler, stream)
+        return value, grad

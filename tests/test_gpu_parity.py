@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Both sides implement the same multiple-double specification and the same
+per-job operation order, so every limb must agree exactly (integer
+comparison of the binary64 bit patterns, signed zeros included).  Cases
+span several workgroup tiles and ragged tails: all seven precisions,
+degrees 0..255, monomials with 1..12 variables, absent variables, N = 0,
+and the benchmark workloads at full size (c1 against a digest of the
+oracle's output written by tests/golden/make_digests.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_bitexact, run_gpu, sha256
+from paper_2101_10881_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("m", W.SUPPORTED_M)
+@pytest.mark.parametrize("op", ["add", "mul"])
+def test_md_elementwise_bitexact(oracle_lib, m, op):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    _say(f"md_elementwise m={m} op={op}")
+    rng = np.random.default_rng(500 + m)
+    count = 20011
+    x = W.md_series(rng, count, m, 0)[:, :, 0]
+    y = W.md_series(rng, count, m, 0)[:, :, 0] * np.ldexp(1.0, rng.integers(-6, 6, size=count))
+    q = count // 10
+    y[:, :q] = -x[:, :q]
+    if m > 1:
+        y[m - 1, :q] = x[m - 1, :q] * 0.25
+    y[:, q:2 * q] = 0.0
+    x, y = np.ascontiguousarray(x), np.ascontiguousarray(y)
+    want = oracle_lib.md_op(op, x, y)
+    dev = torch.device("cuda", 0)
+    xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    zt = torch.empty_like(xt)
+    mdpe.md_elementwise(op, xt, yt, zt)
+    torch.cuda.synchronize()
+    assert_bitexact(zt.cpu().numpy(), want, f"md_{op} m={m}")
+
+
+def _compare(oracle_lib, w):
+    _say(f"eval_and_diff {w.name}: m={w.m} d={w.d} n={w.n} N={w.N}")
+    want_v, want_g = oracle_lib.eval_workload(w)
+    got_v, got_g = run_gpu(w)
+    assert_bitexact(got_v, want_v, f"{w.name} value")
+    assert_bitexact(got_g, want_g, f"{w.name} gradient")
+
+
+@pytest.mark.parametrize("m", W.SUPPORTED_M)
+def test_random_polynomials_bitexact(oracle_lib, m):
+    for seed in range(3):
+        rng = np.random.default_rng(7000 + 10 * m + seed)
+        n = int(rng.integers(1, 14))
+        N = int(rng.integers(1, 40))
+        d = int(rng.choice([0, 1, 2, 5, 8, 17, 33]))
+        nk = rng.integers(1, min(n, 12) + 1, size=N)
+        _compare(oracle_lib, W.random_poly(f"rand_m{m}_s{seed}", m, d, n, N, nk, seed))
+
+
+@pytest.mark.parametrize("d", [0, 1, 7, 31, 63, 64, 65, 100, 152, 200, 255])
+def test_degrees_span_tiles(oracle_lib, d):
+    m = 2 if d > 100 else 3
+    rng = np.random.default_rng(d)
+    w = W.random_poly(f"deg{d}", m, d, 6, 7, rng.integers(1, 6, size=7), seed=d + 1)
+    _compare(oracle_lib, w)
+
+
+def test_many_jobs_ragged_groups(oracle_lib):
+    # J jobs per workgroup with a partial last group in every layer
+    w = W.random_poly("ragged", 4, 9, 12, 61, [5] * 61, seed=3)
+    _compare(oracle_lib, w)
+
+
+def test_edge_cases(oracle_lib):
+    _compare(oracle_lib, W.make("no_monomials", 5, 6, 3, [], seed=2))
+    _compare(oracle_lib, W.make("absent_vars", 4, 5, 9, [(1, 3), (3, 8), (1, 3, 8)], seed=5))
+    _compare(oracle_lib, W.make("one_var", 10, 0, 1, [(0,), (0,)], seed=6))
+    _compare(oracle_lib, W.make("all_vars", 2, 4, 10, [tuple(range(10)), (0, 9)], seed=7))
+    _compare(oracle_lib, W.make("n_k_1_and_2", 3, 3, 4, [(0,), (1, 2), (3,), (0, 3)], seed=8))
+    _compare(oracle_lib, W.make("worked_example", 10, 8, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4))
+
+
+def test_integer_inputs_exact(oracle_lib):
+    rng = np.random.default_rng(9)
+    w = W.random_poly("ints", 4, 6, 5, 9, rng.integers(1, 5, size=9), seed=9)
+    w.coeff[:] = 0.0
+    w.z[:] = 0.0
+    w.coeff[0] = rng.integers(-3, 4, size=w.coeff.shape[1:])
+    w.z[0] = rng.integers(-3, 4, size=w.z.shape[1:])
+    _compare(oracle_lib, w)
+
+
+def test_config0_bitexact(oracle_lib):
+    _compare(oracle_lib, W.config0())
+
+
+def test_config2_bitexact(oracle_lib):
+    _compare(oracle_lib, W.config2())
+
+
+def test_config4_forward_bitexact(oracle_lib):
+    _compare(oracle_lib, W.config4())
+
+
+def test_config1_full_size_digest():
+    # full-size deca-double p1 at d = 152, in the launch configuration the benchmark times
+    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["config1"]
+    w = W.config1()
+    _say(f"eval_and_diff {w.name} (digest)")
+    val, grad = run_gpu(w)
+    assert [float(v).hex() for v in val[:, 0]] == g["value_head"]
+    assert [float(v).hex() for v in grad[:, 0, 0]] == g["grad_head"]
+    assert sha256(val) == g["value_sha256"]
+    assert sha256(grad) == g["grad_sha256"]
+
+
+def test_repeat_and_workspace_reuse(oracle_lib):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = W.random_poly("rep", 5, 20, 7, 15, [3] * 15, seed=12)
+    P = mdpe.Polynomial.for_workload(w, torch.device("cuda", 0))
+    a = run_gpu(w, poly=P)
+    w2 = W.random_poly("rep2", 5, 20, 7, 15, [3] * 15, seed=13)   # same shape, other data, same workspace
+    run_gpu(w2, poly=P)
+    b = run_gpu(w, poly=P)
+    assert_bitexact(a[0], b[0], "repeat value")
+    assert_bitexact(a[1], b[1], "repeat grad")
+    want_v, want_g = oracle_lib.eval_workload(w)
+    assert_bitexact(b[0], want_v, "value")
+
+
+def test_profiled_and_side_stream(oracle_lib):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = W.random_poly("prof", 8, 16, 6, 20, [4] * 20, seed=14)
+    prof = mdpe.Profiler()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = run_gpu(w, profiler=prof)
+    t = prof.read()
+    assert t["n_cnv"] == 4 and t["n_stage"] == 1 and t["n_gather"] == 1
+    assert t["cnv_ms"] > 0
+    want_v, want_g = oracle_lib.eval_workload(w)
+    assert_bitexact(got[0], want_v, "value")
+    assert_bitexact(got[1], want_g, "grad")

@@ -1,0 +1,181 @@
+"""Planner pins (host only, no GPU): the data staging of Section 5.
+
+* The worked example of Section 4 / Fig. 1: 21 convolutions in layers of
+  6, 9, 5, 1; 28 series; the triplet of f_{1,1} and the pair a_0 -> f_{1,3};
+  addition levels 6, 1.
+* The launch sizes and job counts printed for p1, p2 and p3 (Section 6.1,
+  Table 2).
+* eq. (6) for the slot count, 3 n_k - 3 convolutions per monomial,
+  Corollary 2's depth.
+* Executing the plan's jobs on exact rational series reproduces the exact
+  value and gradient (the jobs compute what the paper defines).
+* Invalid descriptions are rejected with the right status.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_ref as E
+from paper_2101_10881_amd import mdpe
+from paper_2101_10881_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _plan(n, supports, d=3, m=2):
+    nvars = [len(s) for s in supports]
+    vars_ = [v for s in supports for v in s]
+    return mdpe.Plan(n, nvars, vars_, d, m, device=-1)
+
+
+def test_worked_example():
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    sup = [tuple(v - 1 for v in s) for s in g["supports_1based"]]
+    p = _plan(g["n"], sup)
+    conv, add = p.layer_sizes()
+    assert p.info["n_conv"] == g["n_conv"]
+    assert conv == g["conv_layer_sizes"]
+    assert add == g["add_level_sizes"]
+    assert p.info["n_series"] == g["n_series"]
+    jobs = p.conv_jobs()
+    assert list(jobs[0][1:]) == g["triplet_f11_in_units_of_d_plus_1"] and jobs[0][0] == 1
+    adds = p.add_jobs()
+    assert list(adds[0][1:]) == g["pair_a0_into_f13_in_units_of_d_plus_1"]
+    # value tree: f13 := a0 + f13, f33 := f24 + f33 (level 1), then f33 := f33 + f13 (level 2)
+    slot = {"a0": 0, "f13": 12, "f24": 16, "f33": 19}
+    want = [(1, slot[a], slot[b]) for a, b in g["value_tree"][:2]] + [(2, slot["f13"], slot["f33"])]
+    got = [tuple(r) for r in adds if r[2] in (slot["f13"], slot["f33"])]
+    assert got == want
+    assert p.outputs()[0] == slot["f33"]
+
+
+def test_p1_counts():
+    g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p1"]
+    p = mdpe.Plan.for_workload(W.config1(), device=-1)
+    conv, add = p.layer_sizes()
+    assert p.info["n_conv"] == g["n_conv"] and p.info["n_add"] == g["n_add"]
+    assert conv == g["conv_launches"] and add == g["add_launches"]
+
+
+def test_p2_counts():
+    g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p2"]
+    p = mdpe.Plan.for_workload(W.config2(), device=-1)
+    conv, add = p.layer_sizes()
+    assert p.info["n_conv"] == g["n_conv"] and p.info["n_add"] == g["n_add"]
+    assert conv[:31] == [g["first_31_conv_launches"]] * 31
+    assert p.info["n_layers"] == 64
+
+
+def test_p3_additions():
+    g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p3"]
+    sup = W.all_subsets(128, 2)
+    assert len(sup) == g["N"]
+    p = _plan(128, sup, d=0, m=1)
+    assert p.info["n_add"] == g["n_add"]
+    assert p.info["n_conv"] == 3 * g["N"]
+
+
+def test_flop_convention_of_the_paper():
+    g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["flops_p1_deca_d152"]
+    from paper_2101_10881_amd import flops
+    d = g["d"]
+    assert 16380 * (d + 1) ** 2 * g["deca_mul_ops"] == g["mul_part"]
+    assert (16380 * d * (d + 1) + 9084 * (d + 1)) * g["deca_add_ops"] == g["add_part"]
+    assert flops.paper_convention(16380, 9084, d) == g["total"]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_counts_eq6_and_corollary2(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 12))
+    N = int(rng.integers(0, 30))
+    nk = rng.integers(1, n + 1, size=N)
+    sup = W.random_supports(rng, n, N, nk)
+    p = _plan(n, sup, d=int(rng.integers(0, 20)), m=int(rng.choice(W.SUPPORTED_M)))
+    i = p.info
+    assert i["n_series"] == 1 + N + n + sum(k + max(1, k - 2) + max(0, k - 2) for k in nk)
+    assert i["n_conv"] == sum(3 * k - 3 if k >= 2 else 1 for k in nk)
+    assert i["n_layers"] == (max(nk) if N else 0)
+    lists = [N + 1] + [sum(1 for s in sup if v in s) for v in range(n)]
+    levels = max(int(np.ceil(np.log2(L))) if L > 1 else 0 for L in lists)
+    assert i["n_levels"] == levels
+    assert i["n_add"] == sum(max(L - 1, 0) for L in lists)
+    out = p.outputs()
+    for v in range(n):
+        assert (out[1 + v] == -1) == (lists[1 + v] == 0)
+
+
+def _execute_exact(p, w):
+    """Run the plan's jobs on exact rational series (slots hold lists of Fractions)."""
+    d = w.d
+    A = [None] * p.info["n_series"]
+    a = E.planar_to_exact(w.coeff)
+    z = E.planar_to_exact(w.z)
+    for s in range(w.N + 1):
+        A[s] = a[s]
+    for i in range(w.n):
+        A[w.N + 1 + i] = z[i]
+    for k, nk in enumerate(w.nvars):   # n_k = 1: the derivative a_k, staged into its backward slot
+        if nk == 1:
+            base = 1 + w.N + w.n + int(sum(w.nvars)) + int(sum(max(1, int(q) - 2) for q in w.nvars[:k]))
+            A[base] = a[k + 1]
+    for layer, t1, t2, t3 in p.conv_jobs():
+        A[t3] = E.smul(A[t1], A[t2])
+    for level, t1, t2 in p.add_jobs():
+        A[t2] = E.sadd(A[t2], A[t1])
+    out = p.outputs()
+    val = A[out[0]]
+    grad = [A[s] if s >= 0 else [Fraction(0)] * (d + 1) for s in out[1:]]
+    return val, grad
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plan_jobs_compute_the_definition(seed):
+    rng = np.random.default_rng(40 + seed)
+    n = int(rng.integers(1, 8))
+    N = int(rng.integers(0, 8))
+    w = W.random_poly("plan", 1, 2, n, N, rng.integers(1, n + 1, size=N), seed)
+    p = mdpe.Plan.for_workload(w, device=-1)
+    val, grad = _execute_exact(p, w)
+    (ev, eg), _ = E.workload_exact(w)
+    assert val == ev
+    assert grad == eg
+
+
+def test_worked_example_jobs_compute_the_definition():
+    w = W.make("ex", 1, 3, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4)
+    val, grad = _execute_exact(mdpe.Plan.for_workload(w, device=-1), w)
+    (ev, eg), _ = E.workload_exact(w)
+    assert val == ev and grad == eg
+
+
+@pytest.mark.parametrize("cfg", ["config0", "config1", "config2", "config4"])
+def test_lane_schedule_is_balanced(cfg):
+    w = getattr(W, cfg)()
+    i = mdpe.Plan.for_workload(w, device=-1).info
+    J, d = i["jobs_per_group"], w.d
+    total = J * (d + 1) * (d + 2) // 2
+    assert i["lane_steps"] >= max(d + 1, -(-total // 64))
+    assert i["lane_steps"] <= max(d + 1, -(-total // 64)) + 1
+
+
+@pytest.mark.parametrize("bad, code", [
+    (dict(n=0), mdpe.MDPE_EINVAL),
+    (dict(nvars=[0]), mdpe.MDPE_EINVAL),
+    (dict(nvars=[4], vars_=[0, 1, 2, 4]), mdpe.MDPE_EINVAL),       # variable out of range
+    (dict(nvars=[2], vars_=[1, 1]), mdpe.MDPE_EINVAL),             # not strictly increasing
+    (dict(nvars=[2], vars_=[2, 1]), mdpe.MDPE_EINVAL),
+    (dict(d=-1), mdpe.MDPE_EINVAL),
+    (dict(m=6), mdpe.MDPE_EUNSUPPORTED),
+    (dict(m=10, d=1100), mdpe.MDPE_EUNSUPPORTED),                  # one job's series exceed LDS
+])
+def test_invalid_descriptions(bad, code):
+    args = dict(n=4, nvars=[2], vars_=[0, 1], d=3, m=2)
+    args.update(bad)
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Plan(args["n"], args["nvars"], args["vars_"], args["d"], args["m"], device=-1)
+    assert e.value.code == code
+    assert mdpe.last_error_string()
