@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark: evaluation + full gradient of p1 in deca-double precision at
+degree 152 (the paper's Table 3 workload) on one MI355X.
+
+One step = one eval_and_diff: staging, the four convolution launches, the
+eleven addition launches and the gather, with inputs already in HBM.
+
+Prints one JSON line.  `value` is the FP64 operation rate of the whole step
+in GFLOP/s, counting the double operations the project's multiple-double
+algorithms execute (FMA = 2) on the convolution jobs without zero terms and
+on the addition jobs.  `roofline` reports the convolution kernel, timed with
+HIP events around each of its launches inside the timed region, against the
+FP64 vector peak.  `cpu_baseline` is the CPU oracle on a bounded sample of
+the same workload, on all host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector, FMA counted as two operations
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one torch copy of this size before timing (for HBM counter calibration)")
+    ap.add_argument("--check", action="store_true", help="compare the output digest with the oracle's")
+    return ap.parse_args()
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("md.hpp", "kernels.hip", "plan.cpp", "plan.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2101_10881_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(digest, launches_per_step):
+    """HBM bytes per convolution launch from the committed PMC summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "conv_layer_kernel_c1_traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != digest:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(target_s):
+    """The oracle, as it stands, on the first K monomials of p1 (m=10, d=152)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2101_10881_amd import flops, mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    cores = len(os.sched_getaffinity(0))
+    full = W.config1()
+
+    def sample(K):
+        sup = full.supports()[:K]
+        w = W.make(f"p1_first{K}", 10, 152, 16, sup, seed=1)
+        t0 = time.perf_counter()
+        O.eval_workload(w, nthreads=cores)
+        dt = time.perf_counter() - t0
+        i = mdpe.Plan.for_workload(w, device=-1).info
+        work = i["n_conv"] * flops.conv_flops(10, 152) + i["n_add"] * flops.add_flops(10, 152)
+        return dt, work
+
+    K0 = max(cores, 8)
+    dt0, _ = sample(K0)
+    K = int(min(1820, max(K0, K0 * target_s / max(dt0, 1e-3))))
+    dt, work = sample(K)
+    return {"value": work / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {K} of the 1820 monomials of p1, m=10, d=152, seed 1 ({dt:.1f} s wall, "
+                      f"{cores} OpenMP threads, same flop accounting as value)",
+            "seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU design is described in DESIGN.md"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2101_10881_amd import flops, mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    w = W.config1()
+    P = mdpe.Polynomial.for_workload(w, dev)
+    info = P.plan.info
+    conv_sizes, add_sizes = P.plan.layer_sizes()
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    value = torch.empty((w.m, w.d + 1), dtype=torch.float64, device=dev)
+    grad = torch.empty((w.m, w.n, w.d + 1), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    if a.copy_calibration_mib:
+        nbytes = a.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(a.warmup):
+        P.eval_and_diff(coeff, z, value, grad)
+    torch.cuda.synchronize()
+
+    prof = mdpe.Profiler()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(a.steps):
+        P.eval_and_diff(coeff, z, value, grad, profiler=prof)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+    kt = prof.read()
+
+    m, d = w.m, w.d
+    step_flops = info["n_conv"] * flops.conv_flops(m, d) + info["n_add"] * flops.add_flops(m, d)
+    ms_per_step = total_ms / a.steps
+    gflops = step_flops / (ms_per_step * 1e-3) / 1e9
+    conv_flops_total = info["n_conv"] * flops.conv_flops(m, d) * a.steps
+    conv_ms = kt["cnv_ms"]
+    achieved = conv_flops_total / (conv_ms * 1e-3) / 1e12
+    launches = kt["n_cnv"]
+    digest = kernel_source_digest()
+    traffic = traffic_from_profile(digest, len(conv_sizes))
+    n_mac = info["n_conv"] * (d + 1) * (d + 2) // 2
+    paper_ops = flops.paper_convention(info["n_conv"], info["n_add"], d)
+
+    out = {
+        "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random deca-double series; p1 supports)",
+        "config": {"workload": w.name, "polynomial": "p1: all 1820 products of 4 of 16 variables",
+                   "m": m, "d": d, "n": w.n, "N": w.N, "seed": 1,
+                   "n_conv": info["n_conv"], "n_add": info["n_add"],
+                   "conv_launches": [int(x) for x in conv_sizes], "add_launches": [int(x) for x in add_sizes]},
+        "roofline": {
+            "kernel": "conv_layer_kernel<10>",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "algorithmic_flops_per_job": flops.conv_flops(m, d),
+            "avg_launch_ms": round(conv_ms / max(launches, 1), 4),
+            "avg_jobs_per_launch": info["n_conv"] / len(conv_sizes),
+            "algorithmic_hbm_GBs": round(info["n_conv"] * flops.conv_bytes(m, d) * a.steps / (conv_ms * 1e-3) / 1e9, 1),
+        },
+        "times_ms_per_step": {"stage": round(kt["stage_ms"] / a.steps, 4), "cnv": round(conv_ms / a.steps, 4),
+                              "add": round(kt["add_ms"] / a.steps, 4), "gather": round(kt["gather_ms"] / a.steps, 4),
+                              "sum": round((conv_ms + kt["add_ms"]) / a.steps, 4),
+                              "wall": round(wall * 1e3 / a.steps, 4)},
+        "md_mac_per_s": round(n_mac / (ms_per_step * 1e-3), 1),
+        "paper_convention_TFLOPs": round(paper_ops / (ms_per_step * 1e-3) / 1e12, 3),
+        "kernel_source_sha256": digest[:16],
+    }
+    if a.check:
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json")))["workloads"]["config1"]
+        h = lambda t: hashlib.sha256(t.cpu().numpy().astype("<f8").tobytes()).hexdigest()
+        out["check"] = {"value_matches_oracle_digest": h(value) == g["value_sha256"],
+                        "grad_matches_oracle_digest": h(grad) == g["grad_sha256"]}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
