@@ -8,8 +8,9 @@
 //
 // Kernels
 //   stage_kernel         user coeff / z -> input slots of A (+ n_k = 1 copies)
-//   conv_layer_kernel<M> one 64-lane workgroup stages J jobs' two input series
-//                        in LDS and computes their J*(d+1) output coefficients;
+//   conv_layer_kernel<M> one 64-lane workgroup stages J jobs' first input series
+//                        in LDS (the second is streamed from L2/HBM one step
+//                        ahead) and computes their J*(d+1) output coefficients;
 //                        each coefficient is one lane's sequential chain
 //                        z_k = x_0 y_k, z_k += x_i y_{k-i} (i = 1..k), and the
 //                        chains are spread over the lanes by a host-made
@@ -34,6 +35,31 @@ namespace mdpe {
 
 // ------------------------------------------------------------------ kernels
 
+// One lane's position in its list of output coefficients.
+struct ChainState {
+    int c;      // index in the lane's chain list
+    int code;   // (job << 16) | k, or -1 when the lane is done
+    int j, k, i;
+    bool live;  // computes a real coefficient (job j exists in this group)
+};
+
+__device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
+    if (st.code >= 0) {
+        st.j = st.code >> 16;
+        st.k = st.code & 0xffff;
+        st.live = st.j < jn;
+    } else {
+        st.j = 0;
+        st.k = 0;
+        st.live = false;
+    }
+    st.i = 0;
+}
+
+// LDS layout of one workgroup: X[J][d+1][M] doubles (the first operands),
+// then the J job descriptors (16-byte aligned).
+__host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
+
 template <int M>
 __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                         int njobs, int d, int J, const int *__restrict__ chains,
@@ -44,64 +70,78 @@ __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, 
     const int g0 = blockIdx.x * J;
     const int jn = min(J, njobs - g0);
     double *X = lds;
-    double *Y = lds + (long)J * S;
+    int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * S));
+    // Stage the first operand of every job in LDS: it is read by all lanes and
+    // may be the job's own output (the in-place b := b * a of Section 3).  The
+    // second operand is never the output (the planner checks) and is streamed
+    // from global memory -- mostly one of the shared input series, so it stays
+    // in L2.  Both operands are fetched one step ahead of their use.
     for (int j = 0; j < jn; ++j) {
         const int4 t = jobs[g0 + j];
         const double *xs = A + (long)t.x * S;
-        const double *ys = A + (long)t.y * S;
-        for (long q = lane; q < S; q += 64) {
-            X[j * S + q] = xs[q];
-            Y[j * S + q] = ys[q];
-        }
+        for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+        if (lane == 0) jd[j] = t;
     }
     __syncthreads();
 
     const int *my = chains + (long)lane * stride;
-    int c = 0;
-    int code = my[0];
-    int j = 0, k = 0, i = 0;
-    bool live = false;
-    if (code >= 0) {
-        j = code >> 16;
-        k = code & 0xffff;
-        live = j < jn;
+    ChainState st;
+    st.c = 0;
+    st.code = my[0];
+    chain_decode(st, jn);
+    int4 job = jd[st.live ? st.j : 0];
+    double xc[M], yc[M];
+    {
+        const double *xp = X + st.j * S;
+        const double *yp = A + (long)job.y * S + (long)st.k * M;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            xc[l] = xp[l];
+            yc[l] = st.live ? yp[l] : 0.0;
+        }
     }
     double acc[M];
     for (int s = 0; s < steps; ++s) {
-        double xv[M], yv[M], p[M];
-        const double *xp = X + j * S + i * M;
-        const double *yp = Y + j * S + (k - i) * M;
-#pragma unroll
-        for (int l = 0; l < M; ++l) {
-            xv[l] = xp[l];
-            yv[l] = yp[l];
+        // next position, and the prefetch of its operands
+        ChainState nx = st;
+        int4 njob = job;
+        if (st.i == st.k) {
+            if (st.code >= 0) nx.code = my[++nx.c];
+            chain_decode(nx, jn);
+            if (nx.live) njob = jd[nx.j];
+        } else {
+            nx.i = st.i + 1;
         }
-        md_mul<M>(xv, yv, p);
-        if (i == 0) {
+        double xn[M], yn[M];
+        {
+            const bool fetch = nx.live && s + 1 < steps;
+            const double *xp = X + nx.j * S + nx.i * M;
+            const double *yp = A + (long)njob.y * S + (long)(nx.k - nx.i) * M;
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                xn[l] = xp[l];
+                yn[l] = fetch ? yp[l] : 0.0;
+            }
+        }
+        double p[M];
+        md_mul<M>(xc, yc, p);
+        if (st.i == 0) {
 #pragma unroll
             for (int l = 0; l < M; ++l) acc[l] = p[l];
         } else {
             md_add<M>(acc, p, acc);
         }
-        if (i == k) {
-            if (live) {
-                double *out = A + (long)jobs[g0 + j].z * S + (long)k * M;
+        if (st.i == st.k && st.live) {
+            double *out = A + (long)job.z * S + (long)st.k * M;
 #pragma unroll
-                for (int l = 0; l < M; ++l) out[l] = acc[l];
-            }
-            if (code >= 0) code = my[++c];
-            if (code >= 0) {
-                j = code >> 16;
-                k = code & 0xffff;
-                live = j < jn;
-            } else {
-                j = 0;
-                k = 0;
-                live = false;
-            }
-            i = 0;
-        } else {
-            ++i;
+            for (int l = 0; l < M; ++l) out[l] = acc[l];
+        }
+        st = nx;
+        job = njob;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            xc[l] = xn[l];
+            yc[l] = yn[l];
         }
     }
 }
@@ -189,6 +229,11 @@ __global__ __launch_bounds__(256) void md_elementwise_kernel(int op, long count,
 // ------------------------------------------------------------------ runtime
 
 namespace {
+
+size_t conv_lds_bytes(int d, int m, int J, int stride) {
+    (void)stride;
+    return (size_t)mdpe::conv_lds_jobs_offset((long)J * (d + 1) * m) + (size_t)J * sizeof(int4);
+}
 
 thread_local std::string g_err;
 
@@ -286,7 +331,7 @@ template <int M>
 int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
-    const size_t lds = (size_t)2 * J * (P.d + 1) * M * sizeof(double);
+    const size_t lds = conv_lds_bytes(P.d, M, J, P.lanes.stride);
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M>,

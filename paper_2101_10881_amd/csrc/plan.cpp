@@ -34,7 +34,7 @@ int choose_jobs_per_group(int d, int m) {
     // LDS budget.
     int need = (2 * kLanes + (d + 2) - 1) / (d + 2);
     need = std::max(1, std::min(need, kLanes));
-    long per_job = 2L * (d + 1) * m * 8;
+    long per_job = (long)(d + 1) * m * 8;
     long cap = std::max(1L, (long)kLdsBudget / per_job);
     return (int)std::max(1L, std::min((long)need, cap));
 }
@@ -113,6 +113,9 @@ static std::string check_hazards(const Plan &P) {
         std::unordered_map<int32_t, int> writer;
         for (size_t q = 0; q < jobs.size(); ++q) {
             int32_t w = jobs[q][2];
+            // the second operand of a convolution is streamed while outputs are
+            // written, so it may never be the job's own output
+            if (stage <= P.n_layers() && jobs[q][1] == w) return "second operand is the output";
             if (w < 0 || w >= P.n_series) return "slot out of range";
             if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
         }
@@ -173,9 +176,9 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         *unsupported = true;
         return "too many series for 32-bit slot indices";
     }
-    if (2L * (d + 1) * m * 8 > kMaxLdsBytes) {
+    if ((long)(d + 1) * m * 8 > kMaxLdsBytes - 32768) {
         *unsupported = true;
-        return "d too large: one convolution job must fit in one workgroup's LDS (2(d+1)m*8 <= 163840 bytes)";
+        return "d too large: one convolution operand must fit in one workgroup's LDS ((d+1)m*8 <= 131072 bytes)";
     }
     if (d + 1 > 65535) {
         *unsupported = true;

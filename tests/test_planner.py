@@ -170,7 +170,7 @@ def test_lane_schedule_is_balanced(cfg):
     (dict(nvars=[2], vars_=[2, 1]), mdpe.MDPE_EINVAL),
     (dict(d=-1), mdpe.MDPE_EINVAL),
     (dict(m=6), mdpe.MDPE_EUNSUPPORTED),
-    (dict(m=10, d=1100), mdpe.MDPE_EUNSUPPORTED),                  # one job's series exceed LDS
+    (dict(m=10, d=2000), mdpe.MDPE_EUNSUPPORTED),                  # one operand series exceeds LDS
 ])
 def test_invalid_descriptions(bad, code):
     args = dict(n=4, nvars=[2], vars_=[0, 1], d=3, m=2)
