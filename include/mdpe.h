@@ -53,8 +53,14 @@ typedef struct {
     const int32_t *nvars;   /* host [N]: n_k, 1 <= n_k <= n */
     const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
                                increasing inside each monomial (Section 4) */
-    uint32_t flags;         /* reserved, must be 0 */
+    uint32_t flags;         /* 0 or MDPE_KEEP_MONOMIAL_VALUES */
 } mdpe_poly_desc;
+
+/* Plan flag: also compute and keep every monomial's product of variables
+ * M_k = prod_{j in monomial k} z_j (one extra convolution per monomial with
+ * n_k >= 2), so that eval_adjoint can run after eval_and_diff.  The value and
+ * gradient are bit-identical with or without it. */
+#define MDPE_KEEP_MONOMIAL_VALUES 1u
 
 /* Plan summary. */
 typedef struct {
@@ -67,6 +73,8 @@ typedef struct {
     int32_t jobs_per_group; /* convolution jobs per 64-lane workgroup */
     int32_t lane_steps;     /* multiply-add steps per lane per workgroup (lane schedule length) */
     int32_t n, N, d, m;
+    int64_t n_reverse;      /* correlation jobs of the reverse pass (0 without the flag) */
+    uint32_t flags;
 } mdpe_plan_info;
 
 /*
@@ -117,6 +125,29 @@ int plan_outputs(const mdpe_plan *plan, int32_t *out_slots);
 int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
                   double *grad, void *workspace, void *stream);
 
+/*
+ * Reverse pass (needs MDPE_KEEP_MONOMIAL_VALUES).  For an upstream adjoint
+ * ybar of the value series, L = sum_t ybar_t p_t, returns
+ *   coeff_bar[k][s] = dL/da_k[s] = sum_{j=0..d-s} ybar[s+j] M_k[j]   (coeff_bar[0] = ybar)
+ *   z_bar[i][s]     = dL/dz_i[s] = sum_{j=0..d-s} ybar[s+j] g_i[j]   (g_i = dp/dz_i)
+ * since p is linear in every input series (Section 4, eq. (3)) and products
+ * are the convolutions of eq. (1).  Each coefficient is md_mul(ybar_s, y_0)
+ * followed by += md_mul(ybar_{s+j}, y_j) in increasing j: one layer of
+ * N + (present variables) correlation jobs on the convolution kernel.
+ *   ybar      device double[m][d+1] (read only)
+ *   workspace the buffer of the preceding eval_and_diff with this plan, on
+ *             the same stream, unmodified since
+ *   coeff_bar device double[m][N+1][d+1] (written)
+ *   z_bar     device double[m][n][d+1] (written; absent variables get +0.0)
+ * The adjoint of an m-double is returned as an m-double: limb 0 is the
+ * double-precision value of the derivative and the lower limbs extend it.
+ */
+int eval_adjoint(const mdpe_plan *plan, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
+                 void *stream);
+
+/* Reverse-pass jobs as rows {t1 (ybar slot), t2 (M_k or gradient slot), t3}. */
+int plan_reverse_jobs(const mdpe_plan *plan, int32_t *rows);
+
 /* Per-kernel timing with HIP events recorded on the launch stream, in the
  * paper's four categories (Section 6.2: convolution, addition, their sum; the
  * caller measures wall time).  Times accumulate over calls until read. */
@@ -130,6 +161,9 @@ int profiler_create(mdpe_profiler **out);
 /* Same as eval_and_diff, with an event pair around every launch. */
 int eval_and_diff_profiled(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
                            double *grad, void *workspace, void *stream, mdpe_profiler *prof);
+/* Same as eval_adjoint, timed (correlation launches count as convolution). */
+int eval_adjoint_profiled(const mdpe_plan *plan, const double *ybar, void *workspace, double *coeff_bar,
+                          double *z_bar, void *stream, mdpe_profiler *prof);
 /* Wait for the recorded events, add their durations into *out, reset. */
 int profiler_read(mdpe_profiler *prof, mdpe_times *out);
 void profiler_destroy(mdpe_profiler *prof);

@@ -437,6 +437,113 @@ int oracle_monomial(int m, int d, int n, int nk, const int *v, const double *a /
     return 0;
 }
 
+/* --------------------------------------------------------- the adjoint -- */
+/*
+ * Reverse pass for an upstream adjoint series ybar of the value series:
+ * L = sum_t ybar_t p_t.  p is linear in every input series, p = z_i * g_i + (terms
+ * free of z_i) with g_i = dp/dz_i, and p = a_k * M_k + (terms free of a_k) with
+ * M_k = prod_{j in monomial k} z_j (eq. (3)); a coefficient s of z_i or a_k then
+ * enters p_t through the coefficient t-s of g_i or M_k (eq. (1)), so
+ *   zbar_i[s] = sum_{j=0..d-s} ybar[s+j] g_i[j],   abar_k[s] = sum_j ybar[s+j] M_k[j],
+ *   abar_0 = ybar.
+ * Each correlation coefficient s is md_mul(ybar_s, y_0), then
+ * += md_mul(ybar_{s+j}, y_j) for j = 1..d-s, in increasing j.
+ * M_k is built like the backward products before the multiplication by a_k:
+ * n_k = 1: z_{i_1};  n_k = 2: z_{i_2} * z_{i_1};  n_k >= 3: b = z_{i_n} * z_{i_{n-1}},
+ * b := b * z_{i_{n-j}} for j = 2..n-2, then M_k = b * z_{i_1}.
+ */
+static void corr(int m, int d, const double *x, const double *y, double *out)
+{
+    double p[MAXM];
+    for (int s = 0; s <= d; ++s) {
+        double *acc = out + (size_t)s * m;
+        md_mul(m, x + (size_t)s * m, y, acc);
+        for (int j = 1; j <= d - s; ++j) {
+            md_mul(m, x + (size_t)(s + j) * m, y + (size_t)j * m, p);
+            md_add(m, acc, p, acc);
+        }
+    }
+}
+
+static void monomial_product(int m, int d, int nk, const int *v, const double *Z, double *M, double *b,
+                             double *tmp)
+{
+    const size_t S = (size_t)(d + 1) * m;
+#define ZS(idx) (Z + (size_t)(idx) * S)
+    if (nk == 1) {
+        memcpy(M, ZS(v[0]), sizeof(double) * S);
+        return;
+    }
+    if (nk == 2) {
+        conv(m, d, ZS(v[1]), ZS(v[0]), M, tmp);
+        return;
+    }
+    conv(m, d, ZS(v[nk - 1]), ZS(v[nk - 2]), b, tmp);
+    for (int j = 2; j <= nk - 2; ++j)
+        conv(m, d, b, ZS(v[nk - 1 - j]), b, tmp);
+    conv(m, d, b, ZS(v[0]), M, tmp);
+#undef ZS
+}
+
+/* coeff_bar [m][N+1][d+1], z_bar [m][n][d+1]; ybar [m][d+1]; grad as returned by
+ * oracle_eval_and_diff for the same inputs. */
+int oracle_eval_adjoint(int m, int d, int n, int N, const int *nvars, const int *vars, const double *z,
+                        const double *grad, const double *ybar, double *coeff_bar, double *z_bar, int nthreads)
+{
+    if (m < 1 || m > MAXM || d < 0 || check_support(n, N, nvars, vars))
+        return -1;
+    const size_t S = (size_t)(d + 1) * m;
+    size_t *start = (size_t *)malloc(sizeof(size_t) * (size_t)(N + 1));
+    size_t tot = 0;
+    for (int k = 0; k < N; ++k) {
+        start[k] = tot;
+        tot += (size_t)nvars[k];
+    }
+    double *Z = (double *)malloc(sizeof(double) * S * (size_t)(n > 0 ? n : 1));
+    double *G = (double *)malloc(sizeof(double) * S * (size_t)(n > 0 ? n : 1));
+    double *Y = (double *)malloc(sizeof(double) * S);
+    from_planar(m, d, n, z, Z);
+    from_planar(m, d, n, grad, G);
+    from_planar(m, d, 1, ybar, Y);
+    to_planar(m, d, N + 1, 0, Y, coeff_bar);
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        double *M = (double *)malloc(sizeof(double) * S * 4);
+        double *b = M + S, *tmp = M + 2 * S, *out = M + 3 * S;
+#pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < N; ++k) {
+            monomial_product(m, d, nvars[k], vars + start[k], Z, M, b, tmp);
+            corr(m, d, Y, M, out);
+            to_planar(m, d, N + 1, k + 1, out, coeff_bar);
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < n; ++i) {
+            int present = 0;
+            for (size_t q = 0; q < tot; ++q)
+                if (vars[q] == i)
+                    present = 1;
+            if (!present) {
+                for (int l = 0; l < m; ++l)
+                    for (int c = 0; c <= d; ++c)
+                        z_bar[((size_t)l * n + i) * (d + 1) + c] = 0.0;
+                continue;
+            }
+            corr(m, d, Y, G + (size_t)i * S, out);
+            to_planar(m, d, n, i, out, z_bar);
+        }
+        free(M);
+    }
+    free(start);
+    free(Z);
+    free(G);
+    free(Y);
+    return 0;
+}
+
 /* ---------------------------------------------- elementwise entry points -- */
 /* x, y, z planar [m][count]; op 0 = add, 1 = mul. */
 int oracle_md_op(int op, int m, long count, const double *x, const double *y, double *z)

@@ -28,6 +28,7 @@ def bind(path):
     L.oracle_eft.argtypes = [ctypes.c_int, ctypes.c_long, _dp, _dp, _dp, _dp]
     L.oracle_op_counts.argtypes = [ctypes.c_int, ctypes.c_int, _lp]
     L.oracle_tree_schedule.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int]
+    L.oracle_eval_adjoint.argtypes = [ctypes.c_int] * 4 + [_ip, _ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
     return L
 
 
@@ -134,3 +135,25 @@ def tree_schedule(length):
         out.append([(int(pairs[2 * (pos + p)]), int(pairs[2 * (pos + p) + 1])) for p in range(sizes[r])])
         pos += int(sizes[r])
     return out
+
+
+def eval_adjoint(m, d, n, nvars, vars_, z, grad, ybar, nthreads=0, L=None):
+    """Adjoints (coeff_bar [m][N+1][d+1], z_bar [m][n][d+1]) of L = sum_t ybar_t p_t.
+    grad: the oracle's gradient for the same inputs."""
+    nvars, vars_ = _i32(nvars), _i32(vars_)
+    N = int(nvars.shape[0])
+    z, grad, ybar = _f64(z), _f64(grad), _f64(ybar)
+    assert ybar.shape == (m, d + 1) and z.shape == (m, n, d + 1) and grad.shape == z.shape
+    cbar = np.empty((m, N + 1, d + 1))
+    zbar = np.empty((m, n, d + 1))
+    rc = (L or lib()).oracle_eval_adjoint(m, d, n, N, _i(nvars), _i(vars_), _d(z), _d(grad), _d(ybar), _d(cbar),
+                                          _d(zbar), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid polynomial description")
+    return cbar, zbar
+
+
+def adjoint_workload(w, ybar, nthreads=0, L=None):
+    """Forward gradient then adjoints, for a workloads.Workload."""
+    _, grad = eval_workload(w, nthreads, L)
+    return eval_adjoint(w.m, w.d, w.n, w.nvars, w.vars, w.z, grad, ybar, nthreads, L)

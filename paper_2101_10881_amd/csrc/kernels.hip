@@ -60,7 +60,11 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
 // then the J job descriptors (16-byte aligned).
 __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
 
-template <int M>
+// CORR = false: convolution z_k = sum_{i=0..k} x_i y_{k-i} (eq. (1)).
+// CORR = true:  correlation z_s = sum_{j=0..d-s} x_{s+j} y_j (the reverse pass);
+//               chain code k then denotes s = d-k, with k+1 terms, x index d-k+i
+//               and y index i, so the same lane schedule balances both.
+template <int M, bool CORR>
 __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                         int njobs, int d, int J, const int *__restrict__ chains,
                                                         int stride, int steps) {
@@ -90,10 +94,12 @@ __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, 
     st.code = my[0];
     chain_decode(st, jn);
     int4 job = jd[st.live ? st.j : 0];
+    auto xidx = [&](int k, int i) { return CORR ? d - k + i : i; };
+    auto yidx = [&](int k, int i) { return CORR ? i : k - i; };
     double xc[M], yc[M];
     {
-        const double *xp = X + st.j * S;
-        const double *yp = A + (long)job.y * S + (long)st.k * M;
+        const double *xp = X + st.j * S + xidx(st.k, 0) * M;
+        const double *yp = A + (long)job.y * S + (long)yidx(st.k, 0) * M;
 #pragma unroll
         for (int l = 0; l < M; ++l) {
             xc[l] = xp[l];
@@ -115,8 +121,8 @@ __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, 
         double xn[M], yn[M];
         {
             const bool fetch = nx.live && s + 1 < steps;
-            const double *xp = X + nx.j * S + nx.i * M;
-            const double *yp = A + (long)njob.y * S + (long)(nx.k - nx.i) * M;
+            const double *xp = X + nx.j * S + xidx(nx.k, nx.i) * M;
+            const double *yp = A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * M;
 #pragma unroll
             for (int l = 0; l < M; ++l) {
                 xn[l] = xp[l];
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, 
             md_add<M>(acc, p, acc);
         }
         if (st.i == st.k && st.live) {
-            double *out = A + (long)job.z * S + (long)st.k * M;
+            double *out = A + (long)job.z * S + (long)(CORR ? d - st.k : st.k) * M;
 #pragma unroll
             for (int l = 0; l < M; ++l) out[l] = acc[l];
         }
@@ -205,6 +211,32 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
     }
 }
 
+// planar [m][count][d+1] series src[e] -> slot dst[e], for e < nentries
+__global__ __launch_bounds__(256) void planar_to_slots_kernel(double *__restrict__ A, const double *__restrict__ src,
+                                                              int count, const int *__restrict__ dst, long total,
+                                                              int d, int m) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int d1 = d + 1;
+    const int e = (int)(idx / d1);
+    const int c = (int)(idx - (long)e * d1);
+    double *to = A + (long)dst[e] * d1 * m + (long)c * m;
+    for (int l = 0; l < m; ++l) to[l] = src[((long)l * count + e) * d1 + c];
+}
+
+// slot slots[e] (or zeros when -1) -> planar [m][count][d+1] series e of dst
+__global__ __launch_bounds__(256) void slots_to_planar_kernel(const double *__restrict__ A, double *__restrict__ dst,
+                                                              int count, const int *__restrict__ slots, int d, int m) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const int d1 = d + 1;
+    if (idx >= (long)count * d1) return;
+    const int e = (int)(idx / d1);
+    const int c = (int)(idx - (long)e * d1);
+    const int slot = slots[e];
+    for (int l = 0; l < m; ++l)
+        dst[((long)l * count + e) * d1 + c] = slot >= 0 ? A[(long)slot * d1 * m + (long)c * m + l] : 0.0;
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void md_elementwise_kernel(int op, long count, const double *__restrict__ x,
                                                              const double *__restrict__ y, double *__restrict__ z) {
@@ -269,6 +301,10 @@ struct mdpe_plan {
     int2 *d_stage = nullptr;
     int *d_out = nullptr;
     int *d_chains = nullptr;
+    int4 *d_corr = nullptr;
+    int *d_cbar = nullptr;
+    int *d_zbar = nullptr;
+    int *d_ybar = nullptr;
 };
 
 struct mdpe_profiler {
@@ -291,15 +327,19 @@ void free_plan(mdpe_plan *p) {
         (void)hipFree(p->d_stage);
         (void)hipFree(p->d_out);
         (void)hipFree(p->d_chains);
+        (void)hipFree(p->d_corr);
+        (void)hipFree(p->d_cbar);
+        (void)hipFree(p->d_zbar);
+        (void)hipFree(p->d_ybar);
     }
     delete p;
 }
 
 template <class T>
 int upload(T **dst, const void *src, size_t bytes) {
-    if (bytes == 0) bytes = sizeof(T);
-    HIP_TRY(hipMalloc((void **)dst, bytes));
-    if (src) HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    // an empty array still gets a (never read) one-element allocation
+    HIP_TRY(hipMalloc((void **)dst, bytes ? bytes : sizeof(T)));
+    if (src && bytes) HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
     return MDPE_OK;
 }
 
@@ -327,28 +367,34 @@ int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
         if (e_ != hipSuccess) return fail(MDPE_EDEVICE, std::string(what ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-template <int M>
-int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+template <int M, bool CORR>
+int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
     const size_t lds = conv_lds_bytes(P.d, M, J, P.lanes.stride);
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M>,
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set = true;
     }
+    if (nj == 0) return MDPE_OK;
+    const int groups = (nj + J - 1) / J;
+    int rc = record(prof, 1, st, true);
+    if (rc) return rc;
+    hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR>), dim3(groups), dim3(64), lds, st, A, jobs, nj, P.d, J,
+                       pl->d_chains, P.lanes.stride, P.lanes.steps);
+    LAUNCH_CHECK("conv_layer_kernel");
+    return record(prof, 1, st, false);
+}
+
+template <int M>
+int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
     for (int L = 1; L <= P.n_layers(); ++L) {
         const long off = P.conv_off[L - 1];
-        const int nj = (int)(P.conv_off[L] - off);
-        if (nj == 0) continue;
-        const int groups = (nj + J - 1) / J;
-        int rc = record(prof, 1, st, true);
+        int rc = launch_layer<M, false>(pl, A, pl->d_conv + off, (int)(P.conv_off[L] - off), st, prof);
         if (rc) return rc;
-        hipLaunchKernelGGL(mdpe::conv_layer_kernel<M>, dim3(groups), dim3(64), lds, st, A, pl->d_conv + off, nj, P.d,
-                           J, pl->d_chains, P.lanes.stride, P.lanes.steps);
-        LAUNCH_CHECK("conv_layer_kernel");
-        if ((rc = record(prof, 1, st, false))) return rc;
     }
     return MDPE_OK;
 }
@@ -422,6 +468,51 @@ int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double 
     return MDPE_OK;
 }
 
+int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
+                 void *stream, mdpe_profiler *prof) {
+    if (!pl) return fail(MDPE_EINVAL, "plan is NULL");
+    if (pl->device < 0) return fail(MDPE_EINVAL, "host-only plan (device -1) cannot evaluate");
+    const mdpe::Plan &P = pl->P;
+    if (!(P.flags & mdpe::kKeepMonomialValues))
+        return fail(MDPE_EINVAL, "the plan was built without MDPE_KEEP_MONOMIAL_VALUES");
+    if (!ybar || !workspace || !coeff_bar || !z_bar) return fail(MDPE_EINVAL, "NULL buffer");
+    if (((uintptr_t)workspace) % 256) return fail(MDPE_EINVAL, "workspace must be 256-byte aligned");
+    DeviceGuard g(pl->device);
+    if (!g.ok) return fail(MDPE_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    double *A = (double *)workspace;
+    const int d1 = P.d + 1;
+    int rc;
+    if ((rc = record(prof, 0, st, true))) return rc;
+    hipLaunchKernelGGL(mdpe::planar_to_slots_kernel, dim3((unsigned)((d1 + 255) / 256)), dim3(256), 0, st, A, ybar, 1,
+                       pl->d_ybar, (long)d1, P.d, P.m);
+    LAUNCH_CHECK("planar_to_slots_kernel");
+    if ((rc = record(prof, 0, st, false))) return rc;
+    const int nj = (int)P.corr.size();
+    switch (P.m) {
+        case 1: rc = launch_layer<1, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 2: rc = launch_layer<2, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 3: rc = launch_layer<3, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 4: rc = launch_layer<4, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 5: rc = launch_layer<5, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 8: rc = launch_layer<8, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 10: rc = launch_layer<10, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
+    }
+    if (rc) return rc;
+    if ((rc = record(prof, 3, st, true))) return rc;
+    {
+        const long tc = (long)(P.N + 1) * d1, tz = (long)P.n * d1;
+        hipLaunchKernelGGL(mdpe::slots_to_planar_kernel, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, st, A,
+                           coeff_bar, P.N + 1, pl->d_cbar, P.d, P.m);
+        LAUNCH_CHECK("slots_to_planar_kernel");
+        hipLaunchKernelGGL(mdpe::slots_to_planar_kernel, dim3((unsigned)((tz + 255) / 256)), dim3(256), 0, st, A,
+                           z_bar, P.n, pl->d_zbar, P.d, P.m);
+        LAUNCH_CHECK("slots_to_planar_kernel");
+    }
+    return record(prof, 3, st, false);
+}
+
 }  // namespace
 
 extern "C" {
@@ -429,14 +520,15 @@ extern "C" {
 int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
-    if (desc->flags != 0) return fail(MDPE_EINVAL, "flags must be 0");
+    if (desc->flags & ~(uint32_t)MDPE_KEEP_MONOMIAL_VALUES) return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
     if (!pl) return fail(MDPE_ENOMEM, "host allocation failed");
     bool unsupported = false;
     std::string err;
     try {
-        err = mdpe::build_plan(desc->n, desc->N, desc->d, desc->m, desc->nvars, desc->vars, pl->P, &unsupported);
+        err = mdpe::build_plan(desc->n, desc->N, desc->d, desc->m, desc->nvars, desc->vars, desc->flags, pl->P,
+                               &unsupported);
     } catch (const std::bad_alloc &) {
         return fail(MDPE_ENOMEM, "host allocation failed while planning");
     }
@@ -451,6 +543,8 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
         const mdpe::Plan &P = pl->P;
         std::vector<int4> conv(P.conv.size());
         for (size_t q = 0; q < P.conv.size(); ++q) conv[q] = make_int4(P.conv[q][0], P.conv[q][1], P.conv[q][2], 0);
+        std::vector<int4> corr(P.corr.size());
+        for (size_t q = 0; q < P.corr.size(); ++q) corr[q] = make_int4(P.corr[q][0], P.corr[q][1], P.corr[q][2], 0);
         std::vector<int2> add(P.add.size()), stage(P.stage.size());
         for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
         for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
@@ -460,7 +554,11 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
             (rc = upload(&raw->d_add, add.data(), add.size() * sizeof(int2))) ||
             (rc = upload(&raw->d_stage, stage.data(), stage.size() * sizeof(int2))) ||
             (rc = upload(&raw->d_out, P.out_slots.data(), P.out_slots.size() * sizeof(int))) ||
-            (rc = upload(&raw->d_chains, P.lanes.chains.data(), P.lanes.chains.size() * sizeof(int)))) {
+            (rc = upload(&raw->d_chains, P.lanes.chains.data(), P.lanes.chains.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_corr, corr.data(), corr.size() * sizeof(int4))) ||
+            (rc = upload(&raw->d_cbar, P.coeff_bar_slots.data(), P.coeff_bar_slots.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_zbar, P.z_bar_slots.data(), P.z_bar_slots.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_ybar, &P.ybar_slot, sizeof(int)))) {
             std::string keep = g_err;
             free_plan(pl.release());
             g_err = keep;
@@ -482,6 +580,8 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->workspace_bytes = P.n_series * (int64_t)(P.d + 1) * P.m * (int64_t)sizeof(double);
     o->jobs_per_group = P.lanes.jobs_per_group;
     o->lane_steps = P.lanes.steps;
+    o->n_reverse = (int64_t)P.corr.size();
+    o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;
     o->d = P.d;
@@ -592,6 +692,25 @@ int md_elementwise(int op, int m, int64_t count, const double *x, const double *
         default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
     }
     LAUNCH_CHECK("md_elementwise_kernel");
+    return MDPE_OK;
+}
+
+int eval_adjoint(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
+                 void *stream) {
+    return adjoint_impl(pl, ybar, workspace, coeff_bar, z_bar, stream, nullptr);
+}
+
+int eval_adjoint_profiled(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar,
+                          double *z_bar, void *stream, mdpe_profiler *prof) {
+    if (!prof) return fail(MDPE_EINVAL, "profiler is NULL");
+    return adjoint_impl(pl, ybar, workspace, coeff_bar, z_bar, stream, prof);
+}
+
+int plan_reverse_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    for (size_t q = 0; q < P.corr.size(); ++q)
+        for (int r = 0; r < 3; ++r) rows[3 * q + r] = P.corr[q][r];
     return MDPE_OK;
 }
 

@@ -115,7 +115,8 @@ static std::string check_hazards(const Plan &P) {
             int32_t w = jobs[q][2];
             // the second operand of a convolution is streamed while outputs are
             // written, so it may never be the job's own output
-            if (stage <= P.n_layers() && jobs[q][1] == w) return "second operand is the output";
+            const bool conv_stage = stage <= P.n_layers() || stage > P.n_layers() + P.n_levels();
+            if (conv_stage && jobs[q][1] == w) return "second operand is the output";
             if (w < 0 || w >= P.n_series) return "slot out of range";
             if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
         }
@@ -143,12 +144,20 @@ static std::string check_hazards(const Plan &P) {
     }
     for (auto s : P.out_slots)
         if (s >= 0 && written[s] < 0) return "output slot never written";
+    if (!P.corr.empty() || P.ybar_slot >= 0) {
+        const int stage = P.n_layers() + P.n_levels() + 1;
+        written[P.ybar_slot] = stage - 1;  // staged before the reverse layer
+        auto e = stage_check(stage, P.corr);
+        if (!e.empty()) return "reverse layer: " + e;
+    }
     return "";
 }
 
-std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, Plan &P,
-                       bool *unsupported) {
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, uint32_t flags,
+                       Plan &P, bool *unsupported) {
     *unsupported = false;
+    if (flags & ~kKeepMonomialValues) return "unknown flags";
+    const bool keep = (flags & kKeepMonomialValues) != 0;
     if (n < 1 || N < 0 || d < 0) return "need n >= 1, N >= 0, d >= 0";
     if (!supported_m(m)) {
         *unsupported = true;
@@ -171,7 +180,10 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         nmax = std::max(nmax, nk);
     }
     const int64_t base = 1 + (int64_t)N + n;
-    const int64_t nser = base + tot + nb + nc;
+    int64_t nmono2 = 0;  // monomials with n_k >= 2: they get an M_k slot when kept
+    for (int k = 0; k < N; ++k) nmono2 += nvars[k] >= 2;
+    const int64_t mbase = base + tot + nb + nc;
+    const int64_t nser = mbase + (keep ? nmono2 + 1 + N + n : 0);
     if (nser > INT32_MAX / 2) {
         *unsupported = true;
         return "too many series for 32-bit slot indices";
@@ -189,14 +201,16 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     P.N = N;
     P.d = d;
     P.m = m;
+    P.flags = flags;
     P.n_series = nser;
 
     std::vector<std::vector<std::array<int32_t, 3>>> layers(std::max(nmax, 1));
     std::vector<int32_t> value_list{0};
     std::vector<std::vector<int32_t>> grad_lists(n);
+    std::vector<int32_t> mono_slot(N, -1);  // slot holding M_k = prod of the monomial's variables
     for (int s = 0; s < 1 + N + n; ++s) P.stage.push_back({s, s});
 
-    int64_t alpha = 0, beta = 0, gamma = 0, pos = 0;
+    int64_t alpha = 0, beta = 0, gamma = 0, pos = 0, mpos = 0;
     for (int k = 0; k < N; ++k) {
         const int nk = nvars[k];
         const int32_t *v = vars + pos;
@@ -211,6 +225,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
             P.stage.push_back({B(1), (int32_t)(k + 1)});
             value_list.push_back(F(1));
             grad_lists[v[0]].push_back(B(1));
+            mono_slot[k] = Z(1);
         } else {
             job(1, A(), Z(1), F(1));
             for (int j = 2; j <= nk; ++j) job(j, F(j - 1), Z(j), F(j));
@@ -218,10 +233,22 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
                 job(1, Z(2), A(), B(1));
                 grad_lists[v[0]].push_back(B(1));
                 grad_lists[v[1]].push_back(F(1));
+                if (keep) {
+                    mono_slot[k] = (int32_t)(mbase + mpos++);
+                    job(1, Z(2), Z(1), mono_slot[k]);  // M_k = z_{i_2} * z_{i_1}
+                }
             } else {
                 job(1, Z(nk), Z(nk - 1), B(1));
                 for (int j = 2; j <= nk - 2; ++j) job(j, B(j - 1), Z(nk - j), B(j));
-                job(nk - 1, B(nk - 2), A(), B(nk - 2));
+                if (keep) {
+                    // M_k = b_{n-2} * z_{i_1} reads the backward product before its
+                    // multiplication by a_k, which therefore moves one layer later
+                    mono_slot[k] = (int32_t)(mbase + mpos++);
+                    job(nk - 1, B(nk - 2), Z(1), mono_slot[k]);
+                    job(nk, B(nk - 2), A(), B(nk - 2));
+                } else {
+                    job(nk - 1, B(nk - 2), A(), B(nk - 2));
+                }
                 for (int j = 1; j <= nk - 3; ++j) job(std::max(j, nk - 2 - j) + 1, F(j), B(nk - 2 - j), C(j));
                 job(nk - 1, F(nk - 2), Z(nk), C(nk - 2));
                 grad_lists[v[0]].push_back(B(nk - 2));
@@ -250,6 +277,24 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     for (auto &r : rounds) {
         P.add.insert(P.add.end(), r.begin(), r.end());
         P.add_off.push_back((int64_t)P.add.size());
+    }
+
+    if (keep) {
+        // reverse pass: abar_k = corr(ybar, M_k), zbar_i = corr(ybar, dp/dz_i)
+        int64_t q = mbase + nmono2;
+        P.ybar_slot = (int32_t)q++;
+        P.coeff_bar_slots.push_back(P.ybar_slot);
+        for (int k = 0; k < N; ++k) {
+            int32_t out = (int32_t)q++;
+            P.corr.push_back({P.ybar_slot, mono_slot[k], out});
+            P.coeff_bar_slots.push_back(out);
+        }
+        for (int i = 0; i < n; ++i) {
+            int32_t out = (int32_t)q++;
+            int32_t g = P.out_slots[1 + i];
+            if (g >= 0) P.corr.push_back({P.ybar_slot, g, out});
+            P.z_bar_slots.push_back(g >= 0 ? out : -1);
+        }
     }
 
     auto err = check_hazards(P);

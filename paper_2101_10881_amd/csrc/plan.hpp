@@ -23,8 +23,11 @@ struct LaneSchedule {
     std::vector<int32_t> chains;
 };
 
+constexpr uint32_t kKeepMonomialValues = 1u;
+
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
+    uint32_t flags = 0;
     int64_t n_series = 0;
     // convolution jobs {t1, t2, t3} in launch order; layer L spans
     // conv[conv_off[L-1] .. conv_off[L])
@@ -37,6 +40,12 @@ struct Plan {
     // staging copies {slot, source}: source s < N+1 is coeff series s, else z series s-N-1
     std::vector<std::array<int32_t, 2>> stage;
     LaneSchedule lanes;
+    // reverse pass (flags & kKeepMonomialValues): one layer of correlation jobs
+    // {t1 = ybar slot, t2 = M_k or gradient slot, t3 = output slot}
+    int32_t ybar_slot = -1;
+    std::vector<std::array<int32_t, 3>> corr;
+    std::vector<int32_t> coeff_bar_slots;   // [N+1]: ybar slot, then abar_k slots
+    std::vector<int32_t> z_bar_slots;       // [n]: zbar_i slot or -1 (absent variable)
 
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
@@ -44,8 +53,8 @@ struct Plan {
 
 // Returns "" on success, else a message; *unsupported distinguishes limits
 // of this implementation from invalid input.
-std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, Plan &out,
-                       bool *unsupported);
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, uint32_t flags,
+                       Plan &out, bool *unsupported);
 
 LaneSchedule make_lane_schedule(int d, int jobs_per_group);
 int choose_jobs_per_group(int d, int m);

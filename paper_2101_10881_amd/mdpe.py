@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmdpe.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdpe.h")
 
 MDPE_OK, MDPE_EINVAL, MDPE_EUNSUPPORTED, MDPE_ENOMEM, MDPE_EDEVICE = 0, -1, -2, -3, -4
+MDPE_KEEP_MONOMIAL_VALUES = 1
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -39,7 +40,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_series", ctypes.c_int64), ("n_conv", ctypes.c_int64), ("n_add", ctypes.c_int64),
                 ("n_layers", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("jobs_per_group", ctypes.c_int32), ("lane_steps", ctypes.c_int32),
-                ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32)]
+                ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +83,9 @@ def lib():
     L.profiler_destroy.argtypes = [_vp]
     L.profiler_destroy.restype = None
     L.md_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp]
+    L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.eval_adjoint_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.plan_reverse_jobs.argtypes = [_vp, _i32p]
     L.plan_destroy.argtypes = [_vp]
     L.plan_destroy.restype = None
     L.last_error_string.argtypes = []
@@ -122,11 +127,11 @@ def _stream(stream):
 class Plan:
     """A plan (plan_polynomial); device -1 builds a host-only plan for inspection."""
 
-    def __init__(self, n, nvars, vars_, d, m, device=0):
+    def __init__(self, n, nvars, vars_, d, m, device=0, flags=0):
         self.nvars = np.ascontiguousarray(nvars, dtype=np.int32)
         self.vars = np.ascontiguousarray(vars_, dtype=np.int32)
         desc = PolyDesc(int(n), int(self.nvars.shape[0]), int(d), int(m),
-                        self.nvars.ctypes.data_as(_i32p), self.vars.ctypes.data_as(_i32p), 0)
+                        self.nvars.ctypes.data_as(_i32p), self.vars.ctypes.data_as(_i32p), int(flags))
         h = _vp()
         _check(lib().plan_polynomial(ctypes.byref(desc), int(device), ctypes.byref(h)))
         self._h = h
@@ -136,14 +141,19 @@ class Plan:
         self.info = info.as_dict()
 
     @classmethod
-    def for_workload(cls, w, device=0):
-        return cls(w.n, w.nvars, w.vars, w.d, w.m, device)
+    def for_workload(cls, w, device=0, flags=0):
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, flags)
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _L is not None:
             _L.plan_destroy(h)
             self._h = None
+
+    def reverse_jobs(self):
+        rows = np.zeros((max(self.info["n_reverse"], 1), 3), dtype=np.int32)
+        _check(lib().plan_reverse_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[: self.info["n_reverse"]]
 
     @property
     def handle(self):
@@ -204,6 +214,16 @@ def eval_and_diff_profiled(plan: Plan, coeff, z, value, grad, workspace, prof: P
                                         _ptr(workspace), _stream(stream), prof._h))
 
 
+def eval_adjoint(plan: Plan, ybar, workspace, coeff_bar, z_bar, stream=None, profiler=None):
+    """Enqueue the reverse pass (plan built with MDPE_KEEP_MONOMIAL_VALUES)."""
+    if profiler is None:
+        _check(lib().eval_adjoint(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(coeff_bar), _ptr(z_bar),
+                                  _stream(stream)))
+    else:
+        _check(lib().eval_adjoint_profiled(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(coeff_bar), _ptr(z_bar),
+                                           _stream(stream), profiler._h))
+
+
 def md_elementwise(op, x, y, z, stream=None):
     """z = x op y on planar [m][count] float64 device tensors; op 'add' or 'mul'."""
     m, count = x.shape
@@ -218,20 +238,36 @@ class Polynomial:
     >>> value, grad = P.eval_and_diff(coeff, z)   # float64 tensors [m][N+1][d+1], [m][n][d+1]
     """
 
-    def __init__(self, n, nvars, vars_, d, m, device=None):
+    def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
-        self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0)
+        flags = MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0
+        self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         nbytes = int(self.plan.info["workspace_bytes"])
         # 256-byte aligned by the caching allocator
         self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
 
     @classmethod
-    def for_workload(cls, w, device=None):
-        return cls(w.n, w.nvars, w.vars, w.d, w.m, device)
+    def for_workload(cls, w, device=None, keep_monomials=False):
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials)
+
+    def new_workspace(self):
+        import torch
+        return torch.empty_like(self.workspace)
+
+    def adjoint(self, ybar, workspace=None, stream=None, profiler=None):
+        """Reverse pass after eval_and_diff on `workspace` (default: this object's)."""
+        import torch
+        if ybar.dtype != torch.float64 or tuple(ybar.shape) != (self.m, self.d + 1) or not ybar.is_contiguous():
+            raise ValueError(f"ybar: need a contiguous float64 tensor of shape {(self.m, self.d + 1)}")
+        cbar = torch.empty((self.m, self.N + 1, self.d + 1), dtype=torch.float64, device=self.device)
+        zbar = torch.empty((self.m, self.n, self.d + 1), dtype=torch.float64, device=self.device)
+        eval_adjoint(self.plan, ybar, self.workspace if workspace is None else workspace, cbar, zbar, stream,
+                     profiler)
+        return cbar, zbar
 
     def _check_inputs(self, coeff, z):
         import torch
@@ -240,15 +276,16 @@ class Polynomial:
             if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
                 raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
 
-    def eval_and_diff(self, coeff, z, value=None, grad=None, stream=None, profiler=None):
+    def eval_and_diff(self, coeff, z, value=None, grad=None, stream=None, profiler=None, workspace=None):
         import torch
         self._check_inputs(coeff, z)
+        ws = self.workspace if workspace is None else workspace
         if value is None:
             value = torch.empty((self.m, self.d + 1), dtype=torch.float64, device=self.device)
         if grad is None:
             grad = torch.empty((self.m, self.n, self.d + 1), dtype=torch.float64, device=self.device)
         if profiler is None:
-            eval_and_diff(self.plan, coeff, z, value, grad, self.workspace, stream)
+            eval_and_diff(self.plan, coeff, z, value, grad, ws, stream)
         else:
-            eval_and_diff_profiled(self.plan, coeff, z, value, grad, self.workspace, profiler, stream)
+            eval_and_diff_profiled(self.plan, coeff, z, value, grad, ws, profiler, stream)
         return value, grad

@@ -1,0 +1,101 @@
+"""GPU reverse pass: eval_adjoint and the torch.autograd.Function, bit for
+bit against the CPU oracle, and against central finite differences of
+L = sum_t ybar_t p_t on leading doubles (step 1e-6)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_ref as E
+from gpu_util import assert_bitexact, run_gpu
+from paper_2101_10881_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_adjoint(w, ybar):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    dev = torch.device("cuda", 0)
+    P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    val, grad = P.eval_and_diff(coeff, z)
+    cbar, zbar = P.adjoint(torch.from_numpy(np.ascontiguousarray(ybar)).to(dev))
+    torch.cuda.synchronize()
+    return val.cpu().numpy(), grad.cpu().numpy(), cbar.cpu().numpy(), zbar.cpu().numpy()
+
+
+def _compare(oracle_lib, w, ybar):
+    print(f"adjoint {w.name}: m={w.m} d={w.d} n={w.n} N={w.N}", flush=True)
+    val, grad, cbar, zbar = _gpu_adjoint(w, ybar)
+    want_v, want_g = oracle_lib.eval_workload(w)
+    assert_bitexact(val, want_v, "value (kept monomials)")
+    assert_bitexact(grad, want_g, "gradient (kept monomials)")
+    want_c, want_z = oracle_lib.eval_adjoint(w.m, w.d, w.n, w.nvars, w.vars, w.z, want_g, ybar)
+    assert_bitexact(cbar, want_c, "coeff_bar")
+    assert_bitexact(zbar, want_z, "z_bar")
+
+
+@pytest.mark.parametrize("m", W.SUPPORTED_M)
+def test_adjoint_random_bitexact(oracle_lib, m):
+    for seed in range(2):
+        rng = np.random.default_rng(800 + 10 * m + seed)
+        n = int(rng.integers(1, 10))
+        N = int(rng.integers(1, 25))
+        d = int(rng.choice([0, 1, 4, 9, 40]))
+        w = W.random_poly(f"adj_m{m}_{seed}", m, d, n, N, rng.integers(1, min(n, 7) + 1, size=N), seed)
+        _compare(oracle_lib, w, W.md_series(rng, 1, m, d)[:, 0, :])
+
+
+def test_adjoint_edge_cases(oracle_lib):
+    _compare(oracle_lib, W.make("adj_absent", 3, 5, 7, [(1, 3), (0,), (1, 3, 6)], seed=3), W.upstream_adjoint(3, 5))
+    _compare(oracle_lib, W.make("adj_const", 2, 4, 2, [], seed=3), W.upstream_adjoint(2, 4))
+    _compare(oracle_lib, W.make("adj_ex", 10, 12, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4),
+             W.upstream_adjoint(10, 12))
+
+
+def test_config4_adjoint_bitexact(oracle_lib):
+    w = W.config4()
+    _compare(oracle_lib, w, W.upstream_adjoint(w.m, w.d, seed=1))
+
+
+def test_autograd_function_matches_oracle_and_finite_differences(oracle_lib):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    from paper_2101_10881_amd.autograd import poly_eval
+    w = W.random_poly("ag", 8, 10, 8, 30, [4] * 30, seed=21)
+    dev = torch.device("cuda", 0)
+    P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
+    coeff = torch.from_numpy(w.coeff).to(dev).requires_grad_(True)
+    z = torch.from_numpy(w.z).to(dev).requires_grad_(True)
+    ybar = W.upstream_adjoint(w.m, w.d, seed=2)
+    value, grad = poly_eval(coeff, z, P)
+    value.backward(torch.from_numpy(ybar).to(dev))
+    torch.cuda.synchronize()
+    want_v, want_g = oracle_lib.eval_workload(w)
+    assert_bitexact(value.detach().cpu().numpy(), want_v, "value")
+    want_c, want_z = oracle_lib.eval_adjoint(w.m, w.d, w.n, w.nvars, w.vars, w.z, want_g, ybar)
+    assert_bitexact(coeff.grad.cpu().numpy(), want_c, "coeff.grad")
+    assert_bitexact(z.grad.cpu().numpy(), want_z, "z.grad")
+    # central differences of L on leading doubles, through the GPU forward
+    zg, cg = z.grad.cpu().numpy(), coeff.grad.cpu().numpy()
+
+    def L(ww):
+        v, _ = run_gpu(ww, poly=P)
+        return sum(Fraction(float(ybar[0, t])) * E.md_value(v[:, t]) for t in range(ww.d + 1))
+
+    rng = np.random.default_rng(5)
+    for kind in ("z", "a", "z", "a"):
+        arr = w.z if kind == "z" else w.coeff
+        idx = int(rng.integers(arr.shape[1]))
+        s = int(rng.integers(w.d + 1))
+        x0 = arr[0, idx, s]
+        out = []
+        for sign in (1, -1):
+            arr[0, idx, s] = x0 + sign * 1e-6
+            out.append((L(w), Fraction(float(arr[0, idx, s])) - Fraction(float(x0))))
+            arr[0, idx, s] = x0
+        fd = (out[0][0] - out[1][0]) / (out[0][1] - out[1][1])
+        adj = E.md_value((zg if kind == "z" else cg)[:, idx, s])
+        assert abs(fd - adj) <= Fraction(1, 10 ** 9) * max(abs(adj), Fraction(1, 10 ** 6)), (kind, idx, s)

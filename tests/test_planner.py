@@ -179,3 +179,54 @@ def test_invalid_descriptions(bad, code):
         mdpe.Plan(args["n"], args["nvars"], args["vars_"], args["d"], args["m"], device=-1)
     assert e.value.code == code
     assert mdpe.last_error_string()
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_keep_monomials_plan_computes_the_adjoint(seed):
+    """With MDPE_KEEP_MONOMIAL_VALUES the forward jobs still compute the value and
+    gradient, and the reverse jobs, run in exact arithmetic, give the adjoints."""
+    rng = np.random.default_rng(90 + seed)
+    n = int(rng.integers(1, 7))
+    N = int(rng.integers(0, 7))
+    nk = rng.integers(1, n + 1, size=N)
+    w = W.random_poly("keep", 1, 2, n, N, nk, seed)
+    p = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_KEEP_MONOMIAL_VALUES)
+    p0 = mdpe.Plan.for_workload(w, device=-1)
+    assert p.info["n_conv"] == p0.info["n_conv"] + int(np.sum(nk >= 2))
+    assert p.info["n_layers"] == p0.info["n_layers"]
+    present = len(set(int(v) for v in w.vars))
+    assert p.info["n_reverse"] == N + present
+    # exact execution: forward jobs, then the reverse correlations
+    d = w.d
+    A = [None] * p.info["n_series"]
+    a = E.planar_to_exact(w.coeff)
+    z = E.planar_to_exact(w.z)
+    for s_ in range(N + 1):
+        A[s_] = a[s_]
+    for i in range(n):
+        A[N + 1 + i] = z[i]
+    for k, q in enumerate(w.nvars):
+        if q == 1:
+            base = 1 + N + n + int(sum(w.nvars)) + int(sum(max(1, int(r) - 2) for r in w.nvars[:k]))
+            A[base] = a[k + 1]
+    for layer, t1, t2, t3 in p.conv_jobs():
+        A[t3] = E.smul(A[t1], A[t2])
+    for level, t1, t2 in p.add_jobs():
+        A[t2] = E.sadd(A[t2], A[t1])
+    ybar = [Fraction(int(v)) for v in rng.integers(-3, 4, size=d + 1)]
+    rj = p.reverse_jobs()
+    A[rj[0][0] if len(rj) else 0] = ybar
+    corr = lambda x, y: [sum((x[s + j] * y[j] for j in range(d + 1 - s)), Fraction(0)) for s in range(d + 1)]
+    for t1, t2, t3 in rj:
+        A[t3] = corr(A[t1], A[t2])
+    (ev, eg), _ = E.workload_exact(w)
+    sup = w.supports()
+    outs = {tuple(r[1:]) for r in rj}
+    for k, s_ in enumerate(sup):
+        M = [Fraction(1)] + [Fraction(0)] * d
+        for v in s_:
+            M = E.smul(M, z[v])
+        assert any(A[t3] == corr(ybar, M) for (t2, t3) in outs), f"abar_{k + 1}"
+    for i in range(n):
+        if any(i in s_ for s_ in sup):
+            assert any(A[t3] == corr(ybar, eg[i]) for (t2, t3) in outs), f"zbar_{i}"
