@@ -175,6 +175,55 @@ void profiler_destroy(mdpe_profiler *prof);
  */
 int md_elementwise(int op, int m, int64_t count, const double *x, const double *y, double *z, void *stream);
 
+/* ------------------------------------------------------- batched plans --
+ * Many polynomials in one persistent launch.  The batch references its plans
+ * (which must outlive it); each instance keeps its own buffers.  All stages
+ * of all instances (staging, convolution layers, addition levels, gather)
+ * become tasks in one queue ordered by pipeline depth; one persistent kernel
+ * of one-wavefront workgroups claims them, and a task waits (acquire) on a
+ * per-instance completion counter for the stages before its own.  Bits are
+ * identical to eval_and_diff of each instance.  Precisions in one batch:
+ * all equal, or {2, 4}.
+ */
+typedef struct mdpe_batch mdpe_batch;
+
+/* Tile choice for instances of precision m and degree d (from the autotuner);
+ * zero fields take the defaults. */
+typedef struct {
+    int32_t m, d;
+    int32_t jobs_per_group;     /* convolution jobs per wavefront pass (lane schedule) */
+    int32_t groups_per_task;    /* passes per convolution task */
+    int32_t add_items_per_task; /* coefficients per addition / staging / gather task */
+} mdpe_batch_tile;
+
+typedef struct {
+    int32_t count;
+    int64_t n_tasks, n_conv_tasks, n_add_tasks;
+    int64_t lds_bytes;
+    int32_t grid;               /* persistent workgroups (known after the first launch) */
+    int32_t m1, m2;
+} mdpe_batch_info;
+
+/* plans[count]: device plans on one device.  tiles may be NULL (ntiles = 0). */
+int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
+               mdpe_batch **out);
+int batch_info(const mdpe_batch *batch, mdpe_batch_info *out);
+/* rows int32[n_tasks][5]: {instance, kind (0 stage, 1 conv, 2 add, 3 gather),
+ * counter threshold, count, first}, in queue order. */
+int batch_tasks(const mdpe_batch *batch, int32_t *rows);
+/* Host arrays [count] of device pointers, same meaning as in eval_and_diff;
+ * copied to the device now (synchronously).  A captured graph reads them at
+ * every replay, so they may change between launches. */
+int batch_set_buffers(mdpe_batch *batch, const double *const *coeff, const double *const *z, double *const *value,
+                      double *const *grad, void *const *workspace);
+/* Enqueue [counter reset, persistent kernel] on stream. */
+int batch_launch(mdpe_batch *batch, void *stream);
+/* Same, as one hipGraph captured at the first call and replayed on stream. */
+int batch_launch_graph(mdpe_batch *batch, void *stream);
+/* Wait for the device and report the persistent kernel's watchdog flag. */
+int batch_status(mdpe_batch *batch);
+void batch_destroy(mdpe_batch *batch);
+
 /* Release a plan (its device job arrays).  NULL is ignored. */
 void plan_destroy(mdpe_plan *plan);
 

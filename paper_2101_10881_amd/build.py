@@ -20,7 +20,7 @@ HIPFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
-SOURCES = ["kernels.hip", "plan.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "plan.cpp"]
 
 
 def hipcc() -> str:

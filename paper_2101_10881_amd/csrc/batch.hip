@@ -1,0 +1,508 @@
+// batch.hip -- many polynomials in one persistent launch.
+//
+// Every instance keeps its own plan (Section 5 job lists), workspace and
+// buffers.  The batch turns all instances' stages -- staging, each
+// convolution layer, each addition level, gathering -- into tasks: a task is
+// a chunk of one stage of one instance, sized to carry enough work to hide
+// its signalling.  The tasks form one queue, ordered by pipeline depth, so a
+// task only ever depends on earlier tasks.
+//
+// One persistent kernel of one-wavefront workgroups (as many as are resident)
+// claims tasks with an atomic counter.  A task of stage s of instance p waits
+// until p's completion counter reaches the number of p's tasks in stages
+// before s (acquire), runs, then increments the counter (release).  Because
+// only running wavefronts claim tasks and dependencies point backwards in the
+// queue, the earliest unfinished task can always run: no deadlock.  A bounded
+// spin turns any unexpected wait into an error flag instead of a hang.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mdpe.h"
+#include "conv_core.hpp"
+#include "plan.hpp"
+#include "runtime.hpp"
+
+namespace mdpe {
+
+struct BatchInst {
+    double *A;
+    const double *coeff;
+    const double *z;
+    double *value;
+    double *grad;
+    const int4 *conv;
+    const int2 *add;
+    const int2 *stage;
+    const int *out;
+    const int *chains;
+    int stride, steps, J;
+    int m, d, n, N;
+};
+
+struct BatchTask {
+    int inst;
+    int kind;   // 0 stage, 1 conv, 2 add, 3 gather
+    int need;   // wait until the instance's completion counter reaches this
+    int count;  // conv: jobs; others: items (coefficients)
+    long first; // conv: first job; add: first (pair, coefficient) item; stage/gather: first item
+};
+
+constexpr int kSpinLimit = 1 << 22;
+
+template <int M>
+__device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, int lane) {
+    const int d1 = I.d + 1;
+    if (T.kind == 1) {
+        for (int g = 0; g < T.count; g += I.J) {
+            conv_group<M, false>(I.A, I.conv + T.first + g, min(I.J, T.count - g), I.J, I.d, lds, I.chains,
+                                 I.stride, I.steps, lane);
+            __syncthreads();
+        }
+    } else {
+        for (int q = lane; q < T.count; q += 64) {
+            const long it = T.first + q;
+            const long e = it / d1;
+            const int c = (int)(it - e * d1);
+            if (T.kind == 0)
+                stage_item(I.A, I.coeff, I.z, I.stage[e], c, I.N, I.n, I.d, M);
+            else if (T.kind == 2)
+                add_item<M>(I.A, I.add[e], c, I.d);
+            else
+                gather_item(I.A, I.value, I.grad, I.out[e], (int)e, c, I.n, I.d, M);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void batch_reset_kernel(int *ctl, int n) {
+    for (int i = threadIdx.x; i < n; i += 64) ctl[i] = 0;
+}
+
+// ctl[0] = next task, ctl[1] = error flag, ctl[2 + p] = completion counter of instance p
+template <int M1, int M2>
+__global__ __launch_bounds__(64) void batch_kernel(const BatchTask *__restrict__ tasks, int ntasks,
+                                                   const BatchInst *__restrict__ insts, int *ctl) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    int *next = ctl, *err = ctl + 1, *done = ctl + 2;
+    while (true) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(next, 1);
+        t = __shfl(t, 0);
+        if (t >= ntasks) break;
+        const BatchTask T = tasks[t];
+        const BatchInst I = insts[T.inst];
+        int ok = 1;
+        if (lane == 0 && T.need > 0) {
+            // poll without invalidating caches; one acquire fence once ready
+            int spins = 0;
+            while (__hip_atomic_load(done + T.inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T.need) {
+                if (++spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (ok)
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            else
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ok = __shfl(ok, 0);
+        if (!ok) break;
+        if (I.m == M1)
+            run_task<M1>(T, I, lds, lane);
+        else
+            run_task<M2>(T, I, lds, lane);
+        // one wavefront per workgroup: the release below waits for all of its
+        // lanes' stores and writes the L2 back before the counter moves
+        if (lane == 0) __hip_atomic_fetch_add(done + T.inst, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+}  // namespace mdpe
+
+// ------------------------------------------------------------------ runtime
+
+namespace {
+
+int bfail(int code, const std::string &msg) {
+    mdpe::set_last_error(msg);
+    return code;
+}
+
+#define BHIP(call)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return bfail(MDPE_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct mdpe_batch {
+    int device = -1;
+    int count = 0;
+    std::vector<mdpe::BatchInst> insts;
+    std::vector<mdpe::BatchTask> tasks;
+    mdpe::BatchInst *d_insts = nullptr;
+    mdpe::BatchTask *d_tasks = nullptr;
+    int *d_ctl = nullptr;
+    std::vector<int *> d_chains;
+    size_t lds = 0;
+    int grid = 0;
+    int m1 = 0, m2 = 0;
+    bool buffers_set = false;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<int> stage_tasks;  // tasks per kind, for batch_info
+};
+
+namespace {
+
+void free_batch(mdpe_batch *b) {
+    if (!b) return;
+    if (b->device < 0) {
+        delete b;
+        return;
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->d_insts);
+    (void)hipFree(b->d_tasks);
+    (void)hipFree(b->d_ctl);
+    for (auto p : b->d_chains) (void)hipFree(p);
+    if (prev >= 0 && b->device >= 0) (void)hipSetDevice(prev);
+    delete b;
+}
+
+// Kernel attributes and the persistent grid (resident one-wavefront
+// workgroups), resolved once, outside any stream capture.
+template <int M1, int M2>
+int prepare_batch(mdpe_batch *b) {
+    static bool attr = false;
+    if (b->lds > 65536 && !attr) {
+        BHIP(hipFuncSetAttribute((const void *)mdpe::batch_kernel<M1, M2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)mdpe::kMaxLdsBytes));
+        attr = true;
+    }
+    if (b->grid == 0) {
+        int per_cu = 0, cus = 0;
+        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)mdpe::batch_kernel<M1, M2>, 64,
+                                                          b->lds));
+        BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+        b->grid = std::max(1, per_cu) * cus;
+        b->grid = std::min<long>(b->grid, (long)b->tasks.size());
+        b->grid = std::max(b->grid, 1);
+    }
+    return MDPE_OK;
+}
+
+template <int M1, int M2>
+int launch_batch(mdpe_batch *b, hipStream_t st, bool prepare_only) {
+    int rc = prepare_batch<M1, M2>(b);
+    if (rc || prepare_only) return rc;
+    hipLaunchKernelGGL(mdpe::batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_ctl, b->count + 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("batch_reset_kernel: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL((mdpe::batch_kernel<M1, M2>), dim3(b->grid), dim3(64), b->lds, st, b->d_tasks,
+                       (int)b->tasks.size(), b->d_insts, b->d_ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("batch_kernel: ") + hipGetErrorString(e));
+    return MDPE_OK;
+}
+
+int launch_any(mdpe_batch *b, hipStream_t st, bool prepare_only = false) {
+#define MS(a, c) (b->m1 == (a) && b->m2 == (c))
+    if (MS(1, 1)) return launch_batch<1, 1>(b, st, prepare_only);
+    if (MS(2, 2)) return launch_batch<2, 2>(b, st, prepare_only);
+    if (MS(3, 3)) return launch_batch<3, 3>(b, st, prepare_only);
+    if (MS(4, 4)) return launch_batch<4, 4>(b, st, prepare_only);
+    if (MS(5, 5)) return launch_batch<5, 5>(b, st, prepare_only);
+    if (MS(8, 8)) return launch_batch<8, 8>(b, st, prepare_only);
+    if (MS(10, 10)) return launch_batch<10, 10>(b, st, prepare_only);
+    if (MS(2, 4)) return launch_batch<2, 4>(b, st, prepare_only);
+#undef MS
+    return bfail(MDPE_EUNSUPPORTED, "batch precisions must be all equal, or {2, 4}");
+}
+
+}  // namespace
+
+extern "C" {
+
+int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
+               mdpe_batch **out) {
+    if (!plans || !out || count <= 0) return bfail(MDPE_EINVAL, "plans, count > 0 and out are required");
+    if (ntiles < 0 || (ntiles > 0 && !tiles)) return bfail(MDPE_EINVAL, "bad tiles");
+    *out = nullptr;
+    std::unique_ptr<mdpe_batch> B(new (std::nothrow) mdpe_batch());
+    if (!B) return bfail(MDPE_ENOMEM, "host allocation failed");
+    B->count = count;
+    std::vector<int> ms;
+    for (int p = 0; p < count; ++p) {
+        if (!plans[p]) return bfail(MDPE_EINVAL, "NULL plan in the batch");
+        const mdpe::Plan *P = &plans[p]->P;
+        int dev = plans[p]->device;
+        if (p == 0) B->device = dev;
+        if (dev != B->device) return bfail(MDPE_EINVAL, "plans on different devices (or host-only mixed in)");
+        if (std::find(ms.begin(), ms.end(), P->m) == ms.end()) ms.push_back(P->m);
+    }
+    std::sort(ms.begin(), ms.end());
+    if (ms.size() == 1) {
+        B->m1 = B->m2 = ms[0];
+    } else if (ms.size() == 2 && ms[0] == 2 && ms[1] == 4) {
+        B->m1 = 2;
+        B->m2 = 4;
+    } else {
+        return bfail(MDPE_EUNSUPPORTED, "batch precisions must be all equal, or {2, 4}");
+    }
+    auto tile_for = [&](int m, int d) {
+        mdpe_batch_tile t{m, d, 0, 0, 0};
+        for (int q = 0; q < ntiles; ++q)
+            if (tiles[q].m == m && tiles[q].d == d) t = tiles[q];
+        if (t.jobs_per_group <= 0) t.jobs_per_group = mdpe::choose_jobs_per_group(d, m);
+        return t;
+    };
+    // schedules per (d, J)
+    std::map<std::pair<int, int>, int> sched_index;
+    std::vector<mdpe::LaneSchedule> scheds;
+    // tasks with their depth and an instance cost for ordering
+    struct Tmp {
+        int depth;
+        double cost;
+        int order;
+        mdpe::BatchTask t;
+    };
+    std::vector<Tmp> tmp;
+    B->insts.resize(count);
+    size_t lds = 0;
+    for (int p = 0; p < count; ++p) {
+        const mdpe::Plan &P = plans[p]->P;
+        const mdpe_batch_tile t = tile_for(P.m, P.d);
+        const int J = t.jobs_per_group;
+        auto key = std::make_pair(P.d, J);
+        if (!sched_index.count(key)) {
+            sched_index[key] = (int)scheds.size();
+            scheds.push_back(mdpe::make_lane_schedule(P.d, J));
+        }
+        const mdpe::LaneSchedule &S = scheds[sched_index[key]];
+        const int G = t.groups_per_task > 0 ? t.groups_per_task : std::max(1, (256 + S.steps - 1) / S.steps);
+        const long items_per_task = t.add_items_per_task > 0 ? t.add_items_per_task : 4096;
+        lds = std::max(lds, (size_t)mdpe::conv_lds_jobs_offset((long)J * (P.d + 1) * P.m) + (size_t)J * 16);
+        mdpe::BatchInst &I = B->insts[p];
+        std::memset(&I, 0, sizeof(I));
+        I.conv = plans[p]->d_conv;
+        I.add = plans[p]->d_add;
+        I.stage = plans[p]->d_stage;
+        I.out = plans[p]->d_out;
+        I.stride = S.stride;
+        I.steps = S.steps;
+        I.J = J;
+        I.m = P.m;
+        I.d = P.d;
+        I.n = P.n;
+        I.N = P.N;
+        const int d1 = P.d + 1;
+        const double cost = (double)P.conv.size() * d1 * d1 * P.m * P.m;
+        int depth = 0, done_before = 0, order = 0;
+        auto emit = [&](int kind, long first, int cnt, int need) {
+            tmp.push_back({depth, cost, order++, {p, kind, need, cnt, first}});
+        };
+        auto items = [&](int kind, long total) {
+            int n = 0;
+            for (long f = 0; f < total; f += items_per_task, ++n)
+                emit(kind, f, (int)std::min(items_per_task, total - f), done_before);
+            return n;
+        };
+        // stage
+        done_before += items(0, (long)P.stage.size() * d1);
+        ++depth;
+        for (int L = 1; L <= P.n_layers(); ++L, ++depth) {
+            const long a = P.conv_off[L - 1], z = P.conv_off[L];
+            int n = 0;
+            for (long f = a; f < z; f += (long)G * J, ++n) emit(1, f, (int)std::min((long)G * J, z - f), done_before);
+            done_before += n;
+        }
+        for (int r = 1; r <= P.n_levels(); ++r, ++depth) {
+            const long a = P.add_off[r - 1] * d1, z = P.add_off[r] * d1;
+            int n = 0;
+            for (long f = a; f < z; f += items_per_task, ++n)
+                emit(2, f, (int)std::min(items_per_task, z - f), done_before);
+            done_before += n;
+        }
+        done_before += items(3, (long)(1 + P.n) * d1);
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &a, const Tmp &b) {
+        if (a.depth != b.depth) return a.depth < b.depth;
+        if (a.cost != b.cost) return a.cost > b.cost;
+        if (a.t.inst != b.t.inst) return a.t.inst < b.t.inst;
+        return a.order < b.order;
+    });
+    for (auto &x : tmp) B->tasks.push_back(x.t);
+    B->lds = lds;
+    B->stage_tasks.assign(4, 0);
+    for (auto &t : B->tasks) B->stage_tasks[t.kind]++;
+    if (B->device < 0) {  // host-only batch: for inspecting the queue
+        *out = B.release();
+        return MDPE_OK;
+    }
+    // device arrays
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(B->device));
+    int rc = MDPE_OK;
+    auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> int {
+        BHIP(hipMalloc(dst, bytes ? bytes : 16));
+        if (bytes) BHIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return MDPE_OK;
+    };
+    for (auto &S : scheds) {
+        int *dc = nullptr;
+        if ((rc = alloc_copy((void **)&dc, S.chains.data(), S.chains.size() * sizeof(int)))) break;
+        B->d_chains.push_back(dc);
+    }
+    if (!rc) {
+        for (int p = 0; p < count; ++p) {
+            const mdpe::Plan &P = plans[p]->P;
+            B->insts[p].chains = B->d_chains[sched_index[{P.d, B->insts[p].J}]];
+        }
+        if (!(rc = alloc_copy((void **)&B->d_tasks, B->tasks.data(), B->tasks.size() * sizeof(mdpe::BatchTask))))
+            if (!(rc = alloc_copy((void **)&B->d_insts, B->insts.data(), B->insts.size() * sizeof(mdpe::BatchInst)))) {
+                // control words: zeroed by the reset kernel before every launch
+                hipError_t e = hipMalloc((void **)&B->d_ctl, sizeof(int) * (size_t)(count + 2));
+                if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+            }
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (rc) {
+        std::string keep = mdpe::get_last_error();
+        free_batch(B.release());
+        mdpe::set_last_error(keep);
+        return rc;
+    }
+    *out = B.release();
+    return MDPE_OK;
+}
+
+int batch_info(const mdpe_batch *b, mdpe_batch_info *o) {
+    if (!b || !o) return bfail(MDPE_EINVAL, "batch and out are required");
+    o->count = b->count;
+    o->n_tasks = (int64_t)b->tasks.size();
+    o->n_conv_tasks = b->stage_tasks[1];
+    o->n_add_tasks = b->stage_tasks[2];
+    o->lds_bytes = (int64_t)b->lds;
+    o->grid = b->grid;
+    o->m1 = b->m1;
+    o->m2 = b->m2;
+    return MDPE_OK;
+}
+
+int batch_tasks(const mdpe_batch *b, int32_t *rows) {
+    if (!b || !rows) return bfail(MDPE_EINVAL, "batch and rows are required");
+    for (size_t q = 0; q < b->tasks.size(); ++q) {
+        const auto &t = b->tasks[q];
+        rows[5 * q] = t.inst;
+        rows[5 * q + 1] = t.kind;
+        rows[5 * q + 2] = t.need;
+        rows[5 * q + 3] = t.count;
+        rows[5 * q + 4] = (int32_t)t.first;
+    }
+    return MDPE_OK;
+}
+
+int batch_set_buffers(mdpe_batch *b, const double *const *coeff, const double *const *z, double *const *value,
+                      double *const *grad, void *const *workspace) {
+    if (!b || !coeff || !z || !value || !grad || !workspace) return bfail(MDPE_EINVAL, "NULL argument");
+    if (b->device < 0) return bfail(MDPE_EINVAL, "host-only batch");
+    for (int p = 0; p < b->count; ++p) {
+        if (!coeff[p] || !z[p] || !value[p] || !grad[p] || !workspace[p])
+            return bfail(MDPE_EINVAL, "NULL buffer for instance " + std::to_string(p));
+        if (((uintptr_t)workspace[p]) % 256) return bfail(MDPE_EINVAL, "workspace must be 256-byte aligned");
+        b->insts[p].A = (double *)workspace[p];
+        b->insts[p].coeff = coeff[p];
+        b->insts[p].z = z[p];
+        b->insts[p].value = value[p];
+        b->insts[p].grad = grad[p];
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(b->device));
+    hipError_t e = hipMemcpy(b->d_insts, b->insts.data(), b->insts.size() * sizeof(mdpe::BatchInst),
+                             hipMemcpyHostToDevice);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    b->buffers_set = true;
+    return MDPE_OK;
+}
+
+int batch_launch(mdpe_batch *b, void *stream) {
+    if (!b) return bfail(MDPE_EINVAL, "batch is NULL");
+    if (!b->buffers_set) return bfail(MDPE_EINVAL, "call batch_set_buffers first");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(b->device));
+    int rc = launch_any(b, (hipStream_t)stream);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return rc;
+}
+
+int batch_launch_graph(mdpe_batch *b, void *stream) {
+    if (!b) return bfail(MDPE_EINVAL, "batch is NULL");
+    if (!b->buffers_set) return bfail(MDPE_EINVAL, "call batch_set_buffers first");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(b->device));
+    int rc = MDPE_OK;
+    if (!b->exec) {
+        // capture [reset, persistent kernel] once on a private stream
+        if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        rc = launch_any(b, b->cap, true);  // attributes and grid, outside the capture
+        if (!rc) {
+            BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            rc = launch_any(b, b->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap, &g);
+            if (!rc && e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            if (!rc) {
+                b->graph = g;
+                e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+    }
+    if (!rc) {
+        hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+        if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return rc;
+}
+
+int batch_status(mdpe_batch *b) {
+    if (!b) return bfail(MDPE_EINVAL, "batch is NULL");
+    if (b->device < 0) return bfail(MDPE_EINVAL, "host-only batch");
+    int flags[2] = {0, 0};
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(b->device));
+    hipError_t e = hipMemcpy(flags, b->d_ctl, sizeof(flags), hipMemcpyDeviceToHost);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    if (flags[1]) return bfail(MDPE_EDEVICE, "batch watchdog: a task waited too long for its inputs");
+    return MDPE_OK;
+}
+
+void batch_destroy(mdpe_batch *b) { free_batch(b); }
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// conv_core.hpp -- device building blocks shared by the per-layer kernels
+// and the persistent batched executor: one wavefront's convolution (or
+// correlation) group, and one coefficient of an addition job.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "md.hpp"
+
+namespace mdpe {
+
+// One lane's position in its list of output coefficients.
+struct ChainState {
+    int c;      // index in the lane's chain list
+    int code;   // (job << 16) | k, or -1 when the lane is done
+    int j, k, i;
+    bool live;  // computes a real coefficient (job j exists in this group)
+};
+
+__device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
+    if (st.code >= 0) {
+        st.j = st.code >> 16;
+        st.k = st.code & 0xffff;
+        st.live = st.j < jn;
+    } else {
+        st.j = 0;
+        st.k = 0;
+        st.live = false;
+    }
+    st.i = 0;
+}
+
+// LDS layout of one workgroup: X[J][d+1][M] doubles (the first operands),
+// then the J job descriptors (16-byte aligned).
+__host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
+
+// CORR = false: convolution z_k = sum_{i=0..k} x_i y_{k-i} (eq. (1)).
+// CORR = true:  correlation z_s = sum_{j=0..d-s} x_{s+j} y_j (the reverse pass);
+//               chain code k then denotes s = d-k, with k+1 terms, x index d-k+i
+//               and y index i, so the same lane schedule balances both.
+// One 64-lane wavefront computes jn <= J jobs jobs[0..jn) (the output
+// coefficients of each spread over the lanes by the schedule `chains`).
+// lds must hold conv_lds_jobs_offset(J*(d+1)*M) + J*16 bytes.  Ends with the
+// wavefront's stores issued (not necessarily complete).
+template <int M, bool CORR>
+__device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
+                                           int d, double *lds, const int *__restrict__ chains, int stride,
+                                           int steps, int lane) {
+    const long S = (long)(d + 1) * M;
+    double *X = lds;
+    int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * S));
+    // Stage the first operand of every job in LDS: it is read by all lanes and
+    // may be the job's own output (the in-place b := b * a of Section 3).  The
+    // second operand is never the output (the planner checks) and is streamed
+    // from global memory -- mostly one of the shared input series, so it stays
+    // in L2.  Both operands are fetched one step ahead of their use.
+    for (int j = 0; j < jn; ++j) {
+        const int4 t = jobs[j];
+        const double *xs = A + (long)t.x * S;
+        for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+        if (lane == 0) jd[j] = t;
+    }
+    __syncthreads();
+
+    const int *my = chains + (long)lane * stride;
+    ChainState st;
+    st.c = 0;
+    st.code = my[0];
+    chain_decode(st, jn);
+    int4 job = jd[st.live ? st.j : 0];
+    auto xidx = [&](int k, int i) { return CORR ? d - k + i : i; };
+    auto yidx = [&](int k, int i) { return CORR ? i : k - i; };
+    double xc[M], yc[M];
+    {
+        const double *xp = X + st.j * S + xidx(st.k, 0) * M;
+        const double *yp = A + (long)job.y * S + (long)yidx(st.k, 0) * M;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            xc[l] = xp[l];
+            yc[l] = st.live ? yp[l] : 0.0;
+        }
+    }
+    double acc[M];
+    for (int s = 0; s < steps; ++s) {
+        // next position, and the prefetch of its operands
+        ChainState nx = st;
+        int4 njob = job;
+        if (st.i == st.k) {
+            if (st.code >= 0) nx.code = my[++nx.c];
+            chain_decode(nx, jn);
+            if (nx.live) njob = jd[nx.j];
+        } else {
+            nx.i = st.i + 1;
+        }
+        double xn[M], yn[M];
+        {
+            const bool fetch = nx.live && s + 1 < steps;
+            const double *xp = X + nx.j * S + xidx(nx.k, nx.i) * M;
+            const double *yp = A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * M;
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                xn[l] = xp[l];
+                yn[l] = fetch ? yp[l] : 0.0;
+            }
+        }
+        double p[M];
+        md_mul<M>(xc, yc, p);
+        if (st.i == 0) {
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc[l] = p[l];
+        } else {
+            md_add<M>(acc, p, acc);
+        }
+        if (st.i == st.k && st.live) {
+            double *out = A + (long)job.z * S + (long)(CORR ? d - st.k : st.k) * M;
+#pragma unroll
+            for (int l = 0; l < M; ++l) out[l] = acc[l];
+        }
+        st = nx;
+        job = njob;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            xc[l] = xn[l];
+            yc[l] = yn[l];
+        }
+    }
+}
+
+template <int M, bool CORR>
+__global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                        int njobs, int d, int J, const int *__restrict__ chains,
+                                                        int stride, int steps) {
+    extern __shared__ double lds[];
+    const int g0 = blockIdx.x * J;
+    conv_group<M, CORR>(A, jobs + g0, min(J, njobs - g0), J, d, lds, chains, stride, steps, threadIdx.x);
+}
+
+// A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).
+template <int M>
+__device__ __forceinline__ void add_item(double *__restrict__ A, int2 t, int c, int d) {
+    const long S = (long)(d + 1) * M;
+    double *up = A + (long)t.y * S + (long)c * M;
+    const double *in = A + (long)t.x * S + (long)c * M;
+    double x[M], y[M], z[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        x[l] = up[l];
+        y[l] = in[l];
+    }
+    md_add<M>(x, y, z);
+#pragma unroll
+    for (int l = 0; l < M; ++l) up[l] = z[l];
+}
+
+// user coefficient / input series -> staged slot (entry (slot, source) at coefficient c)
+__device__ __forceinline__ void stage_item(double *__restrict__ A, const double *__restrict__ coeff,
+                                           const double *__restrict__ z, int2 en, int c, int N, int n, int d, int m) {
+    const int d1 = d + 1;
+    double *dst = A + (long)en.x * d1 * m + (long)c * m;
+    if (en.y <= N) {
+        for (int l = 0; l < m; ++l) dst[l] = coeff[((long)l * (N + 1) + en.y) * d1 + c];
+    } else {
+        const int i = en.y - N - 1;
+        for (int l = 0; l < m; ++l) dst[l] = z[((long)l * n + i) * d1 + c];
+    }
+}
+
+// output o (0 = value, 1+i = d/dz_i) at coefficient c -> user buffers
+__device__ __forceinline__ void gather_item(const double *__restrict__ A, double *__restrict__ value,
+                                            double *__restrict__ grad, int slot, int o, int c, int n, int d, int m) {
+    const int d1 = d + 1;
+    for (int l = 0; l < m; ++l) {
+        const double v = slot >= 0 ? A[(long)slot * d1 * m + (long)c * m + l] : 0.0;
+        if (o == 0)
+            value[(long)l * d1 + c] = v;
+        else
+            grad[((long)l * n + (o - 1)) * d1 + c] = v;
+    }
+}
+
+}  // namespace mdpe

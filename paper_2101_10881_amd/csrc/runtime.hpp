@@ -1,0 +1,29 @@
+// runtime.hpp -- the plan object behind the C ABI and the per-thread error
+// message, shared by the per-layer runtime (kernels.hip) and the batched
+// executor (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "plan.hpp"
+
+struct mdpe_plan {
+    mdpe::Plan P;
+    int device = -1;
+    int4 *d_conv = nullptr;
+    int2 *d_add = nullptr;
+    int2 *d_stage = nullptr;
+    int *d_out = nullptr;
+    int *d_chains = nullptr;
+    int4 *d_corr = nullptr;
+    int *d_cbar = nullptr;
+    int *d_zbar = nullptr;
+    int *d_ybar = nullptr;
+};
+
+namespace mdpe {
+void set_last_error(const std::string &msg);
+const std::string &get_last_error();
+}  // namespace mdpe

@@ -56,6 +56,20 @@ class Times(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchTile(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("jobs_per_group", ctypes.c_int32),
+                ("groups_per_task", ctypes.c_int32), ("add_items_per_task", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n_tasks", ctypes.c_int64), ("n_conv_tasks", ctypes.c_int64),
+                ("n_add_tasks", ctypes.c_int64), ("lds_bytes", ctypes.c_int64), ("grid", ctypes.c_int32),
+                ("m1", ctypes.c_int32), ("m2", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _L = None
@@ -86,6 +100,17 @@ def lib():
     L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.eval_adjoint_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.plan_reverse_jobs.argtypes = [_vp, _i32p]
+    L.plan_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(BatchTile), ctypes.c_int,
+                             ctypes.POINTER(_vp)]
+    L.batch_info.argtypes = [_vp, ctypes.POINTER(BatchInfo)]
+    L.batch_tasks.argtypes = [_vp, _i32p]
+    L.batch_set_buffers.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
+    L.batch_launch.argtypes = [_vp, _vp]
+    L.batch_launch_graph.argtypes = [_vp, _vp]
+    L.batch_status.argtypes = [_vp]
+    L.batch_destroy.argtypes = [_vp]
+    L.batch_destroy.restype = None
     L.plan_destroy.argtypes = [_vp]
     L.plan_destroy.restype = None
     L.last_error_string.argtypes = []
@@ -289,3 +314,78 @@ class Polynomial:
         else:
             eval_and_diff_profiled(self.plan, coeff, z, value, grad, ws, profiler, stream)
         return value, grad
+
+
+class Batch:
+    """plan_batch over Plan objects (kept alive by the batch).
+
+    tiles: optional list of dicts {m, d, jobs_per_group, groups_per_task,
+    add_items_per_task} (zero / missing fields take the defaults).
+    """
+
+    def __init__(self, plans, tiles=None):
+        self.plans = list(plans)
+        arr = (_vp * len(self.plans))(*[p.handle.value for p in self.plans])
+        tl = list(tiles or [])
+        tarr = (BatchTile * max(len(tl), 1))()
+        for q, t in enumerate(tl):
+            tarr[q] = BatchTile(int(t["m"]), int(t["d"]), int(t.get("jobs_per_group", 0)),
+                                int(t.get("groups_per_task", 0)), int(t.get("add_items_per_task", 0)))
+        h = _vp()
+        _check(lib().plan_batch(arr, len(self.plans), tarr, len(tl), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _L is not None:
+            _L.batch_destroy(h)
+            self._h = None
+
+    def info(self):
+        i = BatchInfo()
+        _check(lib().batch_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def tasks(self):
+        n = self.info()["n_tasks"]
+        rows = np.zeros((max(n, 1), 5), dtype=np.int32)
+        _check(lib().batch_tasks(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[:n]
+
+    def set_buffers(self, coeffs, zs, values, grads, workspaces):
+        def arr(ts):
+            return (_vp * len(ts))(*[t.data_ptr() for t in ts])
+        self._keep = (coeffs, zs, values, grads, workspaces)
+        _check(lib().batch_set_buffers(self._h, arr(coeffs), arr(zs), arr(values), arr(grads), arr(workspaces)))
+
+    def launch(self, stream=None):
+        _check(lib().batch_launch(self._h, _stream(stream)))
+
+    def launch_graph(self, stream=None):
+        _check(lib().batch_launch_graph(self._h, _stream(stream)))
+
+    def status(self):
+        _check(lib().batch_status(self._h))
+
+
+class BatchedPolynomials:
+    """Polynomials (one Polynomial each, with its plan and workspace) run as one batch."""
+
+    def __init__(self, workloads, device=None, tiles=None):
+        import torch
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self.polys = [Polynomial.for_workload(w, self.device) for w in workloads]
+        self.batch = Batch([P.plan for P in self.polys], tiles)
+        self.values = [torch.empty((P.m, P.d + 1), dtype=torch.float64, device=self.device) for P in self.polys]
+        self.grads = [torch.empty((P.m, P.n, P.d + 1), dtype=torch.float64, device=self.device) for P in self.polys]
+
+    def bind(self, coeffs, zs):
+        for P, c, z in zip(self.polys, coeffs, zs):
+            P._check_inputs(c, z)
+        self.batch.set_buffers(coeffs, zs, self.values, self.grads, [P.workspace for P in self.polys])
+
+    def run(self, graph=False, stream=None):
+        (self.batch.launch_graph if graph else self.batch.launch)(stream)
+        return self.values, self.grads

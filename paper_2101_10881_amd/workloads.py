@@ -171,3 +171,13 @@ def upstream_adjoint(m: int, d: int, seed: int = 1) -> np.ndarray:
     out = np.zeros((m, d + 1), dtype=np.float64)
     out[0] = rng.uniform(-1.0, 1.0, size=d + 1)
     return out
+
+
+def config3(count: int = 512, seed: int = 1):
+    """The batched configuration: `count` instances with parameters drawn by
+    batch_instances(count, seed), each built from its own seed."""
+    out = []
+    for q, par in enumerate(batch_instances(count, seed)):
+        out.append(random_poly(f"c3_{q}_m{par['m']}_d{par['d']}", par["m"], par["d"], par["n"], par["N"],
+                               par["nk"], par["seed"]))
+    return out

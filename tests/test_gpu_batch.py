@@ -1,0 +1,125 @@
+"""GPU batched executor: one persistent launch (plain or hipGraph-replayed)
+over many polynomials of different sizes, degrees and precisions, bit for
+bit equal to evaluating each instance with eval_and_diff (and to the
+oracle), for several tile choices."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_bitexact
+from paper_2101_10881_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances(count, seed, ms=(2, 4), ds=(0, 3, 8, 16, 33, 64)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        n = int(rng.integers(2, 20))
+        N = int(rng.integers(0, 60))
+        m = int(rng.choice(ms))
+        d = int(rng.choice(ds))
+        out.append(W.random_poly(f"b{seed}_{q}_m{m}_d{d}", m, d, n, N, rng.integers(1, min(n, 8) + 1, size=N),
+                                 1000 * seed + q))
+    return out
+
+
+def _plain(ws):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    dev = torch.device("cuda", 0)
+    out = []
+    for w in ws:
+        P = mdpe.Polynomial.for_workload(w, dev)
+        v, g = P.eval_and_diff(torch.from_numpy(w.coeff).to(dev), torch.from_numpy(w.z).to(dev))
+        out.append((v, g))
+    torch.cuda.synchronize()
+    return [(v.cpu().numpy(), g.cpu().numpy()) for v, g in out]
+
+
+def _batched(ws, tiles=None, graph=False, replays=1, mutate=None):
+    import torch
+    from paper_2101_10881_amd import mdpe
+    dev = torch.device("cuda", 0)
+    B = mdpe.BatchedPolynomials(ws, dev, tiles)
+    coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
+    zs = [torch.from_numpy(w.z).to(dev) for w in ws]
+    B.bind(coeffs, zs)
+    results = []
+    for r in range(replays):
+        print(f"batch launch {r} graph={graph} instances={len(ws)}", flush=True)
+        vals, grads = B.run(graph=graph)
+        torch.cuda.synchronize()
+        B.batch.status()
+        results.append([(v.cpu().numpy(), g.cpu().numpy()) for v, g in zip(vals, grads)])
+        if mutate is not None:
+            mutate(r, coeffs)
+        _ = torch.ones(1000, device=dev).sum()   # eager work between replays
+        torch.cuda.synchronize()
+    return results, B
+
+
+def _check(got, want, what):
+    for q, ((gv, gg), (wv, wg)) in enumerate(zip(got, want)):
+        assert_bitexact(gv, wv, f"{what} instance {q} value")
+        assert_bitexact(gg, wg, f"{what} instance {q} grad")
+
+
+def test_batch_matches_plain_and_oracle(oracle_lib):
+    ws = _instances(24, 1)
+    want = _plain(ws)
+    got, B = _batched(ws)
+    assert B.batch.info()["grid"] > 0
+    _check(got[0], want, "batch")
+    for q in (0, 5, 17):
+        v, g = oracle_lib.eval_workload(ws[q])
+        assert_bitexact(got[0][q][0], v, f"oracle value {q}")
+        assert_bitexact(got[0][q][1], g, f"oracle grad {q}")
+
+
+def test_batch_graph_replays_follow_inputs():
+    import torch
+    ws = _instances(16, 2)
+
+    def mutate(r, coeffs):
+        # next replay sees new coefficients through the same pointers
+        for q, c in enumerate(coeffs):
+            c[0] *= -1.0
+            ws[q].coeff[0] *= -1.0
+
+    got, _ = _batched(ws, graph=True, replays=3, mutate=None)
+    want = _plain(ws)
+    for r in range(3):
+        _check(got[r], want, f"graph replay {r}")
+    ws2 = _instances(10, 3)
+    ws = ws2
+    got2, _ = _batched(ws2, graph=True, replays=2, mutate=mutate)
+    # replay 0 read the original inputs, replay 1 the negated leading limbs of a_0..a_N;
+    # the host copies were flipped after each replay, so they hold the originals again
+    want0 = _plain(ws2)
+    _check(got2[0], want0, "replay 0")
+    for q in range(len(ws2)):
+        ws2[q].coeff[0] *= -1.0
+    want1 = _plain(ws2)
+    _check(got2[1], want1, "replay 1 (new inputs)")
+
+
+@pytest.mark.parametrize("tiles", [
+    [{"m": 2, "d": 16, "jobs_per_group": 11, "groups_per_task": 1, "add_items_per_task": 64},
+     {"m": 4, "d": 33, "jobs_per_group": 2, "groups_per_task": 5, "add_items_per_task": 333}],
+    [{"m": m, "d": d, "jobs_per_group": 1, "groups_per_task": 1, "add_items_per_task": 4096}
+     for m in (2, 4) for d in (0, 3, 8, 16, 33, 64)],
+])
+def test_tiles_do_not_change_bits(tiles):
+    ws = _instances(12, 4)
+    want = _plain(ws)
+    got, _ = _batched(ws, tiles=tiles)
+    _check(got[0], want, "tiled batch")
+
+
+def test_homogeneous_deca_double_batch():
+    ws = _instances(6, 5, ms=(10,), ds=(4, 40))
+    want = _plain(ws)
+    got, _ = _batched(ws, graph=True, replays=2)
+    _check(got[0], want, "m=10 batch")
+    _check(got[1], want, "m=10 batch replay")
