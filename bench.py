@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one torch copy of this size before timing (for HBM counter calibration)")
     ap.add_argument("--check", action="store_true", help="compare the output digest with the oracle's")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
+                    help="c1: p1 deca double d=152 (the headline); c3: 512-instance batch vs separate launches")
+    ap.add_argument("--instances", type=int, default=512, help="c3: number of instances")
     return ap.parse_args()
 
 
@@ -91,11 +94,93 @@ def cpu_baseline(target_s):
             "seconds": dt}
 
 
+def run_c3(a):
+    """The batched configuration: `instances` polynomials (n 8..64, N 16..1024,
+    2..8 variables per monomial, d in {8,16,32,64,128}, m in {2,4}) in one
+    persistent launch (plain and hipGraph-replayed) against one eval_and_diff
+    per instance on one stream.  Outputs must agree bit for bit."""
+    import torch
+
+    from paper_2101_10881_amd import flops, mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    ws = W.config3(a.instances, seed=1)
+    B = mdpe.BatchedPolynomials(ws, dev, tiles=load_tiles())
+    coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
+    zs = [torch.from_numpy(w.z).to(dev) for w in ws]
+    B.bind(coeffs, zs)
+    setup_s = time.perf_counter() - t0
+    work = sum(P.plan.info["n_conv"] * flops.conv_flops(P.m, P.d) + P.plan.info["n_add"] * flops.add_flops(P.m, P.d)
+               for P in B.polys)
+    pv = [torch.empty_like(v) for v in B.values]
+    pg = [torch.empty_like(g) for g in B.grads]
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for P, c, z, v, g in zip(B.polys, coeffs, zs, pv, pg):
+            P.eval_and_diff(c, z, v, g)
+
+    def timed(fn, reps):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_plain = timed(plain, max(1, a.steps // 4))
+    ms_batch = timed(lambda: B.run(graph=False), a.steps)
+    B.batch.status()
+    ms_graph = timed(lambda: B.run(graph=True), a.steps)
+    B.batch.status()
+    same = all(torch.equal(x.view(torch.int64), y.view(torch.int64))
+               for x, y in zip(B.values + B.grads, pv + pg))
+    info = B.batch.info()
+    out = {
+        "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
+        "value": round(work / (ms_graph * 1e-3) / 1e9, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_graph, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random instances)",
+        "config": {"workload": f"c3_batch_{a.instances}", "instances": a.instances, "seed": 1,
+                   "precisions": sorted({P.m for P in B.polys}), "degrees": sorted({P.d for P in B.polys}),
+                   "n_conv": sum(P.plan.info["n_conv"] for P in B.polys),
+                   "n_add": sum(P.plan.info["n_add"] for P in B.polys),
+                   "tasks": info["n_tasks"], "persistent_workgroups": info["grid"]},
+        "batched_ms": {"graph": round(ms_graph, 4), "launch": round(ms_batch, 4)},
+        "plain_ms": round(ms_plain, 4),
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3),
+        "bitexact_vs_plain": bool(same),
+        "setup_s": round(setup_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def load_tiles():
+    """Autotuned tiles for the batched executor, if a cache for this device exists."""
+    path = os.path.join(ROOT, "paper_2101_10881_amd", "tune_cache.json")
+    try:
+        cache = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    return cache.get("gfx950", {}).get("tiles")
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU design is described in DESIGN.md"}))
         sys.exit(2)
+    if a.workload == "c3":
+        return run_c3(a)
     import torch
 
     from paper_2101_10881_amd import flops, mdpe

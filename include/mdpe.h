@@ -179,11 +179,13 @@ int md_elementwise(int op, int m, int64_t count, const double *x, const double *
  * Many polynomials in one persistent launch.  The batch references its plans
  * (which must outlive it); each instance keeps its own buffers.  All stages
  * of all instances (staging, convolution layers, addition levels, gather)
- * become tasks in one queue ordered by pipeline depth; one persistent kernel
- * of one-wavefront workgroups claims them, and a task waits (acquire) on a
- * per-instance completion counter for the stages before its own.  Bits are
- * identical to eval_and_diff of each instance.  Precisions in one batch:
- * all equal, or {2, 4}.
+ * become tasks; each instance goes whole to one of 8 queues, one per XCD,
+ * balanced by estimated cost, ordered by pipeline depth.  One persistent
+ * kernel of one-wavefront workgroups claims the tasks of the XCD it runs on,
+ * and a task waits (acquire) on a per-instance completion counter for the
+ * stages before its own, so producers and consumers of an instance always
+ * share one L2.  Bits are identical to eval_and_diff of each instance.
+ * Precisions in one batch: all equal, or {2, 4}.
  */
 typedef struct mdpe_batch mdpe_batch;
 
@@ -208,8 +210,9 @@ typedef struct {
 int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
                mdpe_batch **out);
 int batch_info(const mdpe_batch *batch, mdpe_batch_info *out);
-/* rows int32[n_tasks][5]: {instance, kind (0 stage, 1 conv, 2 add, 3 gather),
- * counter threshold, count, first}, in queue order. */
+/* rows int32[n_tasks][6]: {instance, kind (0 stage, 1 conv, 2 add, 3 gather),
+ * counter threshold, count, first, queue (XCD)}, queues concatenated, each in
+ * its claim order. */
 int batch_tasks(const mdpe_batch *batch, int32_t *rows);
 /* Host arrays [count] of device pointers, same meaning as in eval_and_diff;
  * copied to the device now (synchronously).  A captured graph reads them at
@@ -220,7 +223,11 @@ int batch_set_buffers(mdpe_batch *batch, const double *const *coeff, const doubl
 int batch_launch(mdpe_batch *batch, void *stream);
 /* Same, as one hipGraph captured at the first call and replayed on stream. */
 int batch_launch_graph(mdpe_batch *batch, void *stream);
-/* Wait for the device and report the persistent kernel's watchdog flag. */
+/* Persistent workgroups to launch (0 = as many as are resident, the default);
+ * for tuning and tests.  Must precede the first batch_launch_graph. */
+int batch_set_grid(mdpe_batch *batch, int grid);
+/* Wait for the device; report the persistent kernel's watchdog flag, or a
+ * queue left undrained because no wavefront ran on its XCD. */
 int batch_status(mdpe_batch *batch);
 void batch_destroy(mdpe_batch *batch);
 

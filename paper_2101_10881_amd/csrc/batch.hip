@@ -7,13 +7,18 @@
 // its signalling.  The tasks form one queue, ordered by pipeline depth, so a
 // task only ever depends on earlier tasks.
 //
-// One persistent kernel of one-wavefront workgroups (as many as are resident)
-// claims tasks with an atomic counter.  A task of stage s of instance p waits
-// until p's completion counter reaches the number of p's tasks in stages
-// before s (acquire), runs, then increments the counter (release).  Because
-// only running wavefronts claim tasks and dependencies point backwards in the
-// queue, the earliest unfinished task can always run: no deadlock.  A bounded
-// spin turns any unexpected wait into an error flag instead of a hang.
+// Instances are spread over one queue per XCD (the MI355X has 8 XCDs, each
+// with its own L2), balancing estimated cost; all tasks of an instance sit in
+// one queue.  One persistent kernel of one-wavefront workgroups (as many as
+// are resident) reads the XCD it runs on from the XCC_ID hardware register
+// and claims tasks of that XCD's queue with an atomic counter.  So every
+// producer/consumer pair of an instance meets in one L2, and cross-XCD cache
+// coherence is never relied on.  A task of stage s of instance p waits until
+// p's completion counter reaches the number of p's tasks in stages before s
+// (acquire), runs, then increments the counter (release).  Because only
+// running wavefronts claim tasks and dependencies point backwards in their
+// queue, the earliest unfinished task of a queue can always run: no deadlock.
+// A bounded spin turns any unexpected wait into an error flag, not a hang.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,11 +59,16 @@ struct BatchTask {
 };
 
 constexpr int kSpinLimit = 1 << 22;
+constexpr int kQueues = 8;  // one task queue per XCD
+
+// the XCD (XCC) this wavefront runs on
+__device__ __forceinline__ int xcd_id() { return (int)(__builtin_amdgcn_s_getreg(20 | (15 << 11)) & (kQueues - 1)); }
 
 template <int M>
 __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, int lane) {
     const int d1 = I.d + 1;
-    if (T.kind == 1) {
+    const int kind = __builtin_amdgcn_readfirstlane(T.kind);
+    if (kind == 1) {
         for (int g = 0; g < T.count; g += I.J) {
             conv_group<M, false>(I.A, I.conv + T.first + g, min(I.J, T.count - g), I.J, I.d, lds, I.chains,
                                  I.stride, I.steps, lane);
@@ -69,9 +79,9 @@ __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, in
             const long it = T.first + q;
             const long e = it / d1;
             const int c = (int)(it - e * d1);
-            if (T.kind == 0)
+            if (kind == 0)
                 stage_item(I.A, I.coeff, I.z, I.stage[e], c, I.N, I.n, I.d, M);
-            else if (T.kind == 2)
+            else if (kind == 2)
                 add_item<M>(I.A, I.add[e], c, I.d);
             else
                 gather_item(I.A, I.value, I.grad, I.out[e], (int)e, c, I.n, I.d, M);
@@ -83,45 +93,57 @@ __global__ __launch_bounds__(64) void batch_reset_kernel(int *ctl, int n) {
     for (int i = threadIdx.x; i < n; i += 64) ctl[i] = 0;
 }
 
-// ctl[0] = next task, ctl[1] = error flag, ctl[2 + p] = completion counter of instance p
+// ctl[q] = next task of queue q, ctl[kQueues] = error flag,
+// ctl[kQueues + 1 + p] = completion counter of instance p.
+// qinfo[q] = first task of queue q, qinfo[kQueues + q] = its task count.
 template <int M1, int M2>
-__global__ __launch_bounds__(64) void batch_kernel(const BatchTask *__restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(64) void batch_kernel(const BatchTask *__restrict__ tasks, const int *__restrict__ qinfo,
                                                    const BatchInst *__restrict__ insts, int *ctl) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
-    int *next = ctl, *err = ctl + 1, *done = ctl + 2;
-    while (true) {
+    const int q = xcd_id();
+    const int qbase = qinfo[q], qcount = qinfo[kQueues + q];
+    int *next = ctl + q, *err = ctl + kQueues, *done = ctl + kQueues + 1;
+    // Every value that steers control flow is made wave-uniform (scalar), so
+    // the task loop is one scalar loop, never a per-lane divergent one.
+    for (;;) {
         int t = 0;
         if (lane == 0) t = atomicAdd(next, 1);
-        t = __shfl(t, 0);
-        if (t >= ntasks) break;
-        const BatchTask T = tasks[t];
-        const BatchInst I = insts[T.inst];
-        int ok = 1;
-        if (lane == 0 && T.need > 0) {
-            // poll without invalidating caches; one acquire fence once ready
-            int spins = 0;
-            while (__hip_atomic_load(done + T.inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T.need) {
-                if (++spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= qcount) break;
+        const BatchTask T = tasks[qbase + t];
+        const int inst = __builtin_amdgcn_readfirstlane(T.inst);
+        const int need = __builtin_amdgcn_readfirstlane(T.need);
+        if (need > 0) {
+            // poll without invalidating caches, then one acquire fence
+            int spins = 0, ok = 1;
+            for (;;) {
+                const int v = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(done + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (v >= need) break;
+                const int e = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (e || ++spins > kSpinLimit) {
                     ok = 0;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
-            if (ok)
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            else
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!ok) {
+                if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        ok = __shfl(ok, 0);
-        if (!ok) break;
-        if (I.m == M1)
+        const BatchInst I = insts[inst];
+        if (__builtin_amdgcn_readfirstlane(I.m) == M1)
             run_task<M1>(T, I, lds, lane);
         else
             run_task<M2>(T, I, lds, lane);
-        // one wavefront per workgroup: the release below waits for all of its
-        // lanes' stores and writes the L2 back before the counter moves
-        if (lane == 0) __hip_atomic_fetch_add(done + T.inst, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // release: the fence waits for this wavefront's stores and writes the
+        // L2 back; then lane 0 moves the instance's completion counter
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_fetch_add(done + inst, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -151,10 +173,14 @@ struct mdpe_batch {
     std::vector<mdpe::BatchTask> tasks;
     mdpe::BatchInst *d_insts = nullptr;
     mdpe::BatchTask *d_tasks = nullptr;
+    int *d_qinfo = nullptr;
     int *d_ctl = nullptr;
+    std::vector<int> qinfo;      // [2 * kQueues]: first task, task count per queue
+    std::vector<int> inst_queue; // queue of each instance
     std::vector<int *> d_chains;
     size_t lds = 0;
     int grid = 0;
+    bool grid_fixed = false;
     int m1 = 0, m2 = 0;
     bool buffers_set = false;
     hipGraphExec_t exec = nullptr;
@@ -179,6 +205,7 @@ void free_batch(mdpe_batch *b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_tasks);
+    (void)hipFree(b->d_qinfo);
     (void)hipFree(b->d_ctl);
     for (auto p : b->d_chains) (void)hipFree(p);
     if (prev >= 0 && b->device >= 0) (void)hipSetDevice(prev);
@@ -200,9 +227,8 @@ int prepare_batch(mdpe_batch *b) {
         BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)mdpe::batch_kernel<M1, M2>, 64,
                                                           b->lds));
         BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+        // every XCD needs resident wavefronts to drain its queue
         b->grid = std::max(1, per_cu) * cus;
-        b->grid = std::min<long>(b->grid, (long)b->tasks.size());
-        b->grid = std::max(b->grid, 1);
     }
     return MDPE_OK;
 }
@@ -211,11 +237,11 @@ template <int M1, int M2>
 int launch_batch(mdpe_batch *b, hipStream_t st, bool prepare_only) {
     int rc = prepare_batch<M1, M2>(b);
     if (rc || prepare_only) return rc;
-    hipLaunchKernelGGL(mdpe::batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_ctl, b->count + 2);
+    hipLaunchKernelGGL(mdpe::batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_ctl, b->count + mdpe::kQueues + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("batch_reset_kernel: ") + hipGetErrorString(e));
-    hipLaunchKernelGGL((mdpe::batch_kernel<M1, M2>), dim3(b->grid), dim3(64), b->lds, st, b->d_tasks,
-                       (int)b->tasks.size(), b->d_insts, b->d_ctl);
+    hipLaunchKernelGGL((mdpe::batch_kernel<M1, M2>), dim3(b->grid), dim3(64), b->lds, st, b->d_tasks, b->d_qinfo,
+                       b->d_insts, b->d_ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("batch_kernel: ") + hipGetErrorString(e));
     return MDPE_OK;
@@ -277,11 +303,32 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
     std::vector<mdpe::LaneSchedule> scheds;
     // tasks with their depth and an instance cost for ordering
     struct Tmp {
+        int queue;
         int depth;
         double cost;
         int order;
         mdpe::BatchTask t;
     };
+    // estimated cost per instance (multiply-adds x limbs^2), then longest-first
+    // assignment of instances to the XCD queues
+    std::vector<double> icost(count);
+    for (int p = 0; p < count; ++p) {
+        const mdpe::Plan &P = plans[p]->P;
+        const double d1 = P.d + 1;
+        icost[p] = ((double)P.conv.size() * d1 * (d1 + 1) / 2 + (double)P.add.size() * d1) * P.m * P.m + d1;
+    }
+    std::vector<int> order_p(count);
+    for (int p = 0; p < count; ++p) order_p[p] = p;
+    std::stable_sort(order_p.begin(), order_p.end(), [&](int a, int c) { return icost[a] > icost[c]; });
+    std::vector<double> qload(mdpe::kQueues, 0.0);
+    B->inst_queue.assign(count, 0);
+    for (int p : order_p) {
+        int best = 0;
+        for (int q = 1; q < mdpe::kQueues; ++q)
+            if (qload[q] < qload[best]) best = q;
+        qload[best] += icost[p];
+        B->inst_queue[p] = best;
+    }
     std::vector<Tmp> tmp;
     B->insts.resize(count);
     size_t lds = 0;
@@ -312,10 +359,11 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         I.n = P.n;
         I.N = P.N;
         const int d1 = P.d + 1;
-        const double cost = (double)P.conv.size() * d1 * d1 * P.m * P.m;
+        const double cost = icost[p];
+        const int queue = B->inst_queue[p];
         int depth = 0, done_before = 0, order = 0;
         auto emit = [&](int kind, long first, int cnt, int need) {
-            tmp.push_back({depth, cost, order++, {p, kind, need, cnt, first}});
+            tmp.push_back({queue, depth, cost, order++, {p, kind, need, cnt, first}});
         };
         auto items = [&](int kind, long total) {
             int n = 0;
@@ -342,12 +390,18 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         done_before += items(3, (long)(1 + P.n) * d1);
     }
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &a, const Tmp &b) {
+        if (a.queue != b.queue) return a.queue < b.queue;
         if (a.depth != b.depth) return a.depth < b.depth;
         if (a.cost != b.cost) return a.cost > b.cost;
         if (a.t.inst != b.t.inst) return a.t.inst < b.t.inst;
         return a.order < b.order;
     });
-    for (auto &x : tmp) B->tasks.push_back(x.t);
+    B->qinfo.assign(2 * mdpe::kQueues, 0);
+    for (size_t q = 0; q < tmp.size(); ++q) {
+        B->tasks.push_back(tmp[q].t);
+        B->qinfo[mdpe::kQueues + tmp[q].queue]++;
+    }
+    for (int q = 1; q < mdpe::kQueues; ++q) B->qinfo[q] = B->qinfo[q - 1] + B->qinfo[mdpe::kQueues + q - 1];
     B->lds = lds;
     B->stage_tasks.assign(4, 0);
     for (auto &t : B->tasks) B->stage_tasks[t.kind]++;
@@ -375,10 +429,11 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
             const mdpe::Plan &P = plans[p]->P;
             B->insts[p].chains = B->d_chains[sched_index[{P.d, B->insts[p].J}]];
         }
-        if (!(rc = alloc_copy((void **)&B->d_tasks, B->tasks.data(), B->tasks.size() * sizeof(mdpe::BatchTask))))
+        if (!(rc = alloc_copy((void **)&B->d_tasks, B->tasks.data(), B->tasks.size() * sizeof(mdpe::BatchTask))) &&
+            !(rc = alloc_copy((void **)&B->d_qinfo, B->qinfo.data(), B->qinfo.size() * sizeof(int))))
             if (!(rc = alloc_copy((void **)&B->d_insts, B->insts.data(), B->insts.size() * sizeof(mdpe::BatchInst)))) {
                 // control words: zeroed by the reset kernel before every launch
-                hipError_t e = hipMalloc((void **)&B->d_ctl, sizeof(int) * (size_t)(count + 2));
+                hipError_t e = hipMalloc((void **)&B->d_ctl, sizeof(int) * (size_t)(count + mdpe::kQueues + 1));
                 if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
             }
     }
@@ -410,11 +465,12 @@ int batch_tasks(const mdpe_batch *b, int32_t *rows) {
     if (!b || !rows) return bfail(MDPE_EINVAL, "batch and rows are required");
     for (size_t q = 0; q < b->tasks.size(); ++q) {
         const auto &t = b->tasks[q];
-        rows[5 * q] = t.inst;
-        rows[5 * q + 1] = t.kind;
-        rows[5 * q + 2] = t.need;
-        rows[5 * q + 3] = t.count;
-        rows[5 * q + 4] = (int32_t)t.first;
+        rows[6 * q] = t.inst;
+        rows[6 * q + 1] = t.kind;
+        rows[6 * q + 2] = t.need;
+        rows[6 * q + 3] = t.count;
+        rows[6 * q + 4] = (int32_t)t.first;
+        rows[6 * q + 5] = b->inst_queue[t.inst];
     }
     return MDPE_OK;
 }
@@ -492,14 +548,26 @@ int batch_launch_graph(mdpe_batch *b, void *stream) {
 int batch_status(mdpe_batch *b) {
     if (!b) return bfail(MDPE_EINVAL, "batch is NULL");
     if (b->device < 0) return bfail(MDPE_EINVAL, "host-only batch");
-    int flags[2] = {0, 0};
+    int flags[mdpe::kQueues + 1] = {0};
     int prev = -1;
     (void)hipGetDevice(&prev);
     BHIP(hipSetDevice(b->device));
+    BHIP(hipDeviceSynchronize());
     hipError_t e = hipMemcpy(flags, b->d_ctl, sizeof(flags), hipMemcpyDeviceToHost);
     if (prev >= 0) (void)hipSetDevice(prev);
     if (e != hipSuccess) return bfail(MDPE_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
-    if (flags[1]) return bfail(MDPE_EDEVICE, "batch watchdog: a task waited too long for its inputs");
+    if (flags[mdpe::kQueues]) return bfail(MDPE_EDEVICE, "batch watchdog: a task waited too long for its inputs");
+    for (int q = 0; q < mdpe::kQueues; ++q)
+        if (flags[q] < b->qinfo[mdpe::kQueues + q])
+            return bfail(MDPE_EDEVICE, "batch queue " + std::to_string(q) + " was not drained (no wavefront ran on its XCD)");
+    return MDPE_OK;
+}
+
+int batch_set_grid(mdpe_batch *b, int grid) {
+    if (!b || grid < 0) return bfail(MDPE_EINVAL, "batch is NULL or grid < 0");
+    if (b->exec) return bfail(MDPE_EINVAL, "the batch's graph is already captured");
+    b->grid = grid;  // 0: resident capacity, resolved at the next launch
+    b->grid_fixed = grid > 0;
     return MDPE_OK;
 }
 

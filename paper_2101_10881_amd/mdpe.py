@@ -109,6 +109,7 @@ def lib():
     L.batch_launch.argtypes = [_vp, _vp]
     L.batch_launch_graph.argtypes = [_vp, _vp]
     L.batch_status.argtypes = [_vp]
+    L.batch_set_grid.argtypes = [_vp, ctypes.c_int]
     L.batch_destroy.argtypes = [_vp]
     L.batch_destroy.restype = None
     L.plan_destroy.argtypes = [_vp]
@@ -348,7 +349,7 @@ class Batch:
 
     def tasks(self):
         n = self.info()["n_tasks"]
-        rows = np.zeros((max(n, 1), 5), dtype=np.int32)
+        rows = np.zeros((max(n, 1), 6), dtype=np.int32)
         _check(lib().batch_tasks(self._h, rows.ctypes.data_as(_i32p)))
         return rows[:n]
 
@@ -366,6 +367,9 @@ class Batch:
 
     def status(self):
         _check(lib().batch_status(self._h))
+
+    def set_grid(self, grid):
+        _check(lib().batch_set_grid(self._h, int(grid)))
 
 
 class BatchedPolynomials:

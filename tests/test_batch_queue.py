@@ -30,10 +30,13 @@ def test_queue_covers_and_orders(tiles):
     rows = B.tasks()
     assert B.info()["m1"] == 2 and B.info()["m2"] == 4
     seen_before = {}
-    for inst, kind, need, count, first in rows:
-        # waits only for earlier tasks of its own instance
+    queue_of = {}
+    for inst, kind, need, count, first, queue in rows:
+        # waits only for earlier tasks of its own instance, all in one queue
         assert need <= seen_before.get(inst, 0)
         seen_before[inst] = seen_before.get(inst, 0) + 1
+        assert queue_of.setdefault(inst, queue) == queue
+    assert list(rows[:, 5]) == sorted(rows[:, 5])
     for p, w in enumerate(ws):
         mine = rows[rows[:, 0] == p]
         kinds = list(mine[:, 1])
@@ -43,12 +46,12 @@ def test_queue_covers_and_orders(tiles):
         d1 = w.d + 1
         conv = mine[mine[:, 1] == 1]
         covered = np.zeros(info["n_conv"], dtype=int)
-        for _, _, _, c, f in conv:
+        for _, _, _, c, f, _ in conv:
             covered[f:f + c] += 1
         assert np.all(covered == 1)
         add = mine[mine[:, 1] == 2]
         items = np.zeros(info["n_add"] * d1, dtype=int)
-        for _, _, _, c, f in add:
+        for _, _, _, c, f, _ in add:
             items[f:f + c] += 1
         assert np.all(items == 1)
         st = mine[mine[:, 1] == 0]

@@ -37,11 +37,13 @@ def _plain(ws):
     return [(v.cpu().numpy(), g.cpu().numpy()) for v, g in out]
 
 
-def _batched(ws, tiles=None, graph=False, replays=1, mutate=None):
+def _batched(ws, tiles=None, graph=False, replays=1, mutate=None, grid=0):
     import torch
     from paper_2101_10881_amd import mdpe
     dev = torch.device("cuda", 0)
     B = mdpe.BatchedPolynomials(ws, dev, tiles)
+    if grid:
+        B.batch.set_grid(grid)
     coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
     zs = [torch.from_numpy(w.z).to(dev) for w in ws]
     B.bind(coeffs, zs)
@@ -123,3 +125,16 @@ def test_homogeneous_deca_double_batch():
     got, _ = _batched(ws, graph=True, replays=2)
     _check(got[0], want, "m=10 batch")
     _check(got[1], want, "m=10 batch replay")
+
+
+@pytest.mark.parametrize("grid", [8, 64])
+def test_wavefronts_running_many_tasks(grid):
+    # a small persistent grid makes every wavefront claim and run many tasks in turn
+    # (one per XCD at grid 8), the regime of the full 512-instance batch
+    ws = _instances(12, 6)
+    small = [{"m": m, "d": d, "groups_per_task": 1, "add_items_per_task": 64} for m in (2, 4)
+             for d in (0, 3, 8, 16, 33, 64)]
+    want = _plain(ws)
+    got, _ = _batched(ws, tiles=small, grid=grid, graph=True, replays=2)
+    _check(got[0], want, f"grid {grid}")
+    _check(got[1], want, f"grid {grid} replay")
