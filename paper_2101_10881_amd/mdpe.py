@@ -388,7 +388,14 @@ class BatchedPolynomials:
     def bind(self, coeffs, zs):
         for P, c, z in zip(self.polys, coeffs, zs):
             P._check_inputs(c, z)
+        self._inputs = (coeffs, zs)
         self.batch.set_buffers(coeffs, zs, self.values, self.grads, [P.workspace for P in self.polys])
+
+    def set_tiles(self, tiles):
+        """Rebuild the task queue with other tiles (plans and buffers are kept)."""
+        self.batch = Batch([P.plan for P in self.polys], tiles)
+        if getattr(self, "_inputs", None) is not None:
+            self.bind(*self._inputs)
 
     def run(self, graph=False, stream=None):
         (self.batch.launch_graph if graph else self.batch.launch)(stream)
