@@ -37,15 +37,21 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one torch copy of this size before timing (for HBM counter calibration)")
     ap.add_argument("--check", action="store_true", help="compare the output digest with the oracle's")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
-                    help="c1: p1 deca double d=152 (the headline); c3: 512-instance batch vs separate launches")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "sweep"],
+                    help="c1: p1 deca double d=152 (the headline); c3: 512-instance batch vs separate launches; "
+                         "sweep: the paper's precision x degree tables for p1, p2, p3")
+    ap.add_argument("--polys", default="p1,p2,p3", help="sweep: test polynomials")
+    ap.add_argument("--ms", default="1,2,3,4,5,8,10", help="sweep: precisions")
+    ap.add_argument("--ds", default="0,8,15,31,63,95,127,152,159,191", help="sweep: degrees")
     ap.add_argument("--instances", type=int, default=512, help="c3: number of instances")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-vs-plain (c3) and autograd (c4) side measurements")
     return ap.parse_args()
 
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("md.hpp", "kernels.hip", "plan.cpp", "plan.hpp"):
+    for f in ("md.hpp", "conv_core.hpp", "kernels.hip", "plan.cpp", "plan.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2101_10881_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -94,7 +100,7 @@ def cpu_baseline(target_s):
             "seconds": dt}
 
 
-def run_c3(a):
+def measure_c3(instances, steps, warmup):
     """The batched configuration: `instances` polynomials (n 8..64, N 16..1024,
     2..8 variables per monomial, d in {8,16,32,64,128}, m in {2,4}) in one
     persistent launch (plain and hipGraph-replayed) against one eval_and_diff
@@ -106,7 +112,7 @@ def run_c3(a):
 
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    ws = W.config3(a.instances, seed=1)
+    ws = W.config3(instances, seed=1)
     B = mdpe.BatchedPolynomials(ws, dev, tiles=load_tiles())
     coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
     zs = [torch.from_numpy(w.z).to(dev) for w in ws]
@@ -123,7 +129,7 @@ def run_c3(a):
             P.eval_and_diff(c, z, v, g)
 
     def timed(fn, reps):
-        for _ in range(a.warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -134,34 +140,122 @@ def run_c3(a):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_plain = timed(plain, max(1, a.steps // 4))
-    ms_batch = timed(lambda: B.run(graph=False), a.steps)
+    ms_plain = timed(plain, max(1, steps // 4))
+    ms_batch = timed(lambda: B.run(graph=False), steps)
     B.batch.status()
-    ms_graph = timed(lambda: B.run(graph=True), a.steps)
+    ms_graph = timed(lambda: B.run(graph=True), steps)
     B.batch.status()
     same = all(torch.equal(x.view(torch.int64), y.view(torch.int64))
                for x, y in zip(B.values + B.grads, pv + pg))
     info = B.batch.info()
-    out = {
-        "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
-        "value": round(work / (ms_graph * 1e-3) / 1e9, 1),
-        "unit": "GFLOP/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(ms_graph, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded random instances)",
-        "config": {"workload": f"c3_batch_{a.instances}", "instances": a.instances, "seed": 1,
-                   "precisions": sorted({P.m for P in B.polys}), "degrees": sorted({P.d for P in B.polys}),
-                   "n_conv": sum(P.plan.info["n_conv"] for P in B.polys),
-                   "n_add": sum(P.plan.info["n_add"] for P in B.polys),
-                   "tasks": info["n_tasks"], "persistent_workgroups": info["grid"]},
+    return {
+        "workload": f"c3_batch_{instances}", "instances": instances, "seed": 1,
+        "GFLOPs": round(work / (ms_graph * 1e-3) / 1e9, 1),
         "batched_ms": {"graph": round(ms_graph, 4), "launch": round(ms_batch, 4)},
         "plain_ms": round(ms_plain, 4),
         "speedup_vs_plain": round(ms_plain / ms_graph, 3),
         "bitexact_vs_plain": bool(same),
+        "precisions": sorted({P.m for P in B.polys}), "degrees": sorted({P.d for P in B.polys}),
+        "n_conv": sum(P.plan.info["n_conv"] for P in B.polys), "n_add": sum(P.plan.info["n_add"] for P in B.polys),
+        "tasks": info["n_tasks"], "persistent_workgroups": info["grid"], "tiles": "autotuned" if load_tiles() else "default",
         "setup_s": round(setup_s, 1),
     }
+
+
+def run_c3(a):
+    r = measure_c3(a.instances, a.steps, a.warmup)
+    out = {
+        "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
+        "value": r["GFLOPs"], "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": r["batched_ms"]["graph"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random instances)",
+        "config": {"workload": r["workload"]},
+        "batched": r,
+    }
     print(json.dumps(out), flush=True)
+
+
+def measure_c4(steps, warmup):
+    """The differentiation configuration: octo-double p1 at d = 32; forward
+    (eval_and_diff keeping the monomial products) and the reverse pass."""
+    import torch
+
+    from paper_2101_10881_amd import mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    w = W.config4()
+    P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    ybar = torch.from_numpy(W.upstream_adjoint(w.m, w.d, seed=1)).to(dev)
+    for _ in range(warmup):
+        P.eval_and_diff(coeff, z)
+        P.adjoint(ybar)
+    torch.cuda.synchronize()
+    prof = mdpe.Profiler()
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    for _ in range(steps):
+        P.eval_and_diff(coeff, z)
+    e[1].record(stream)
+    for _ in range(steps):
+        P.adjoint(ybar, profiler=prof)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    t = prof.read()
+    return {"workload": w.name, "forward_ms": round(e[0].elapsed_time(e[1]) / steps, 4),
+            "reverse_ms": round(e[1].elapsed_time(e[2]) / steps, 4),
+            "reverse_correlation_ms": round(t["cnv_ms"] / steps, 4),
+            "reverse_jobs": P.plan.info["n_reverse"], "forward_conv_jobs": P.plan.info["n_conv"]}
+
+
+def sweep_workload(poly, m, d):
+    from paper_2101_10881_amd import workloads as W
+    return {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d)
+
+
+def run_sweep(a):
+    """The structure of the paper's appendix tables: for each test polynomial,
+    precision and degree, the summed convolution and addition kernel times,
+    their sum and the wall time of one evaluation, in milliseconds."""
+    import torch
+
+    from paper_2101_10881_amd import flops, mdpe
+
+    dev = torch.device("cuda", 0)
+    rows = []
+    for poly in a.polys.split(","):
+        for m in (int(x) for x in a.ms.split(",")):
+            for d in (int(x) for x in a.ds.split(",")):
+                w = sweep_workload(poly, m, d)
+                P = mdpe.Polynomial.for_workload(w, dev)
+                coeff = torch.from_numpy(w.coeff).to(dev)
+                z = torch.from_numpy(w.z).to(dev)
+                v, g = P.eval_and_diff(coeff, z)
+                torch.cuda.synchronize()
+                reps = max(1, a.steps)
+                prof = mdpe.Profiler()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    P.eval_and_diff(coeff, z, v, g, profiler=prof)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) * 1e3 / reps
+                t = prof.read()
+                info = P.plan.info
+                work = info["n_conv"] * flops.conv_flops(m, d) + info["n_add"] * flops.add_flops(m, d)
+                row = {"poly": poly, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
+                       "add_ms": round(t["add_ms"] / reps, 4), "sum_ms": round((t["cnv_ms"] + t["add_ms"]) / reps, 4),
+                       "wall_ms": round(wall, 4), "n_conv": info["n_conv"], "n_add": info["n_add"],
+                       "TFLOPs": round(work / (t["cnv_ms"] + t["add_ms"]) * reps / 1e9, 3)}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+                del P, coeff, z, v, g
+                torch.cuda.empty_cache()
+    print(json.dumps({"sweep": rows}), flush=True)
 
 
 def load_tiles():
@@ -181,6 +275,8 @@ def main():
         sys.exit(2)
     if a.workload == "c3":
         return run_c3(a)
+    if a.workload == "sweep":
+        return run_sweep(a)
     import torch
 
     from paper_2101_10881_amd import flops, mdpe
@@ -278,6 +374,9 @@ def main():
         h = lambda t: hashlib.sha256(t.cpu().numpy().astype("<f8").tobytes()).hexdigest()
         out["check"] = {"value_matches_oracle_digest": h(value) == g["value_sha256"],
                         "grad_matches_oracle_digest": h(grad) == g["grad_sha256"]}
+    if not a.no_extras:
+        out["batched_vs_plain"] = measure_c3(a.instances, 3, 1)
+        out["autograd_c4"] = measure_c4(10, 2)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
