@@ -14,6 +14,9 @@
  * and all partial derivatives dp/dz_i, where every product is the truncated
  * convolution of eq. (1) (Section 2), in m-fold double arithmetic.
  *
+ * Coefficients and inputs are real m-doubles, or complex ones whose real and
+ * imaginary parts are kept apart (Sections 2 and 5); see cmd_mul below.
+ *
  * Per monomial it runs the forward / backward / cross product recipe of
  * Section 3 (statement list and the n=5 example, eq. (2)), with the index
  * readings listed in the design notes: the forward chain multiplies by
@@ -128,36 +131,87 @@ static void md_mul(int m, const double *x, const double *y, double *z)
     renorm(m, S, z);
 }
 
+/* ------------------------------------------------- complex m-doubles -- */
+/*
+ * Complex coefficients (Section 2 and Section 5 keep real and imaginary parts
+ * in separate arrays): a complex m-double is its real part, an m-double, then
+ * its imaginary part, 2m doubles.  The product is the textbook
+ *   (xr + xi i)(yr + yi i) = (xr yr - xi yi) + (xr yi + xi yr) i
+ * with every product one md_mul; the real part is md_add(xr yr, -(xi yi)),
+ * where the negation flips the sign of every limb (exact), and the imaginary
+ * part is md_add(xr yi, xi yr).  The sum adds the two parts separately.
+ * z may alias x or y.
+ */
+static void cmd_mul(int m, const double *x, const double *y, double *z)
+{
+    double rr[MAXM], ii[MAXM], ri[MAXM], ir[MAXM];
+    md_mul(m, x, y, rr);
+    md_mul(m, x + m, y + m, ii);
+    md_mul(m, x, y + m, ri);
+    md_mul(m, x + m, y, ir);
+    for (int l = 0; l < m; ++l)
+        ii[l] = -ii[l];
+    md_add(m, rr, ii, z);
+    md_add(m, ri, ir, z + m);
+}
+
+static void cmd_add(int m, const double *x, const double *y, double *z)
+{
+    md_add(m, x, y, z);
+    md_add(m, x + m, y + m, z + m);
+}
+
+/* One coefficient operation of the series' number field: cx = 0 real, 1 complex. */
+static void coef_mul(int m, int cx, const double *x, const double *y, double *z)
+{
+    if (cx)
+        cmd_mul(m, x, y, z);
+    else
+        md_mul(m, x, y, z);
+}
+
+static void coef_add(int m, int cx, const double *x, const double *y, double *z)
+{
+    if (cx)
+        cmd_add(m, x, y, z);
+    else
+        md_add(m, x, y, z);
+}
+
 /* ------------------------------------------------------------ series ops -- */
-/* A series is (d+1) coefficients of m limbs: s[c*m + l]. */
+/* A series is (d+1) coefficients of w doubles, w = m (real) or 2m (complex:
+ * real limbs, then imaginary limbs): s[c*w + l]. */
 
 /* z = x * y truncated at degree d (Section 2, eq. (1)): for each k,
  * z_k = x_0*y_k, then z_k += x_i*y_{k-i} for i = 1..k in increasing i.
  * z may alias x or y (the in-place update b := b * a of Section 3). */
-static void conv(int m, int d, const double *x, const double *y, double *z, double *tmp)
+static void conv(int m, int cx, int d, const double *x, const double *y, double *z, double *tmp)
 {
-    double p[MAXM];
+    const size_t w = (size_t)m << cx;
+    double p[2 * MAXM];
     for (int k = 0; k <= d; ++k) {
-        double *acc = tmp + (size_t)k * m;
-        md_mul(m, x, y + (size_t)k * m, acc);
+        double *acc = tmp + (size_t)k * w;
+        coef_mul(m, cx, x, y + (size_t)k * w, acc);
         for (int i = 1; i <= k; ++i) {
-            md_mul(m, x + (size_t)i * m, y + (size_t)(k - i) * m, p);
-            md_add(m, acc, p, acc);
+            coef_mul(m, cx, x + (size_t)i * w, y + (size_t)(k - i) * w, p);
+            coef_add(m, cx, acc, p, acc);
         }
     }
-    memcpy(z, tmp, sizeof(double) * (size_t)(d + 1) * m);
+    memcpy(z, tmp, sizeof(double) * (size_t)(d + 1) * w);
 }
 
 /* upd := upd + inp, coefficientwise (Section 2, last paragraph; Section 5 addition job). */
-static void series_add(int m, int d, double *upd, const double *inp)
+static void series_add(int m, int cx, int d, double *upd, const double *inp)
 {
+    const size_t w = (size_t)m << cx;
     for (int k = 0; k <= d; ++k)
-        md_add(m, upd + (size_t)k * m, inp + (size_t)k * m, upd + (size_t)k * m);
+        coef_add(m, cx, upd + (size_t)k * w, inp + (size_t)k * w, upd + (size_t)k * w);
 }
 
 /* ---------------------------------------------------------- layout glue -- */
 
-/* planar [m][count][d+1] -> series-major [count][(d+1)*m] */
+/* planar [w][count][d+1] -> series-major [count][(d+1)*w]; w = m, or 2m for
+ * complex data, whose planes are the m real limbs, then the m imaginary ones */
 static void from_planar(int m, int d, int count, const double *src, double *dst)
 {
     for (int s = 0; s < count; ++s)
@@ -182,10 +236,10 @@ static void to_planar(int m, int d, int count, int idx, const double *ser, doubl
  * Z holds the n input series (series-major).  Work arrays: f, b, c of
  * nk series each, tmp one series.
  */
-static void monomial(int m, int d, int nk, const int *v, const double *a, const double *Z,
+static void monomial(int m, int cx, int d, int nk, const int *v, const double *a, const double *Z,
                      double *val, double **der, double *f, double *b, double *c, double *tmp)
 {
-    const size_t S = (size_t)(d + 1) * m;
+    const size_t S = (size_t)(d + 1) * ((size_t)m << cx);
 #define ZS(idx) (Z + (size_t)(idx) * S)
 #define F(j) (f + (size_t)((j) - 1) * S)  /* 1-based as in the paper */
 #define B(j) (b + (size_t)((j) - 1) * S)
@@ -193,18 +247,18 @@ static void monomial(int m, int d, int nk, const int *v, const double *a, const 
 #define I(j) (v[(j) - 1])                  /* i_j, 1-based position */
     const int n = nk;
     if (n == 1) {
-        conv(m, d, a, ZS(I(1)), F(1), tmp);
+        conv(m, cx, d, a, ZS(I(1)), F(1), tmp);
         memcpy(val, F(1), sizeof(double) * S);
         memcpy(der[0], a, sizeof(double) * S);
         return;
     }
     /* forward products: f_1 = a * z_{i_1}; f_j = f_{j-1} * z_{i_j} */
-    conv(m, d, a, ZS(I(1)), F(1), tmp);
+    conv(m, cx, d, a, ZS(I(1)), F(1), tmp);
     for (int j = 2; j <= n; ++j)
-        conv(m, d, F(j - 1), ZS(I(j)), F(j), tmp);
+        conv(m, cx, d, F(j - 1), ZS(I(j)), F(j), tmp);
     if (n == 2) {
         /* b_1 = z_{i_2} * a (the n_k = 2 case of Section 5) */
-        conv(m, d, ZS(I(2)), a, B(1), tmp);
+        conv(m, cx, d, ZS(I(2)), a, B(1), tmp);
         memcpy(val, F(2), sizeof(double) * S);
         memcpy(der[0], B(1), sizeof(double) * S);
         memcpy(der[1], F(1), sizeof(double) * S);
@@ -212,14 +266,14 @@ static void monomial(int m, int d, int nk, const int *v, const double *a, const 
     }
     /* backward products: b_1 = z_{i_n} * z_{i_{n-1}}; b_j = b_{j-1} * z_{i_{n-j}};
        then b_{n-2} := b_{n-2} * a */
-    conv(m, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);
+    conv(m, cx, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);
     for (int j = 2; j <= n - 2; ++j)
-        conv(m, d, B(j - 1), ZS(I(n - j)), B(j), tmp);
-    conv(m, d, B(n - 2), a, B(n - 2), tmp);
+        conv(m, cx, d, B(j - 1), ZS(I(n - j)), B(j), tmp);
+    conv(m, cx, d, B(n - 2), a, B(n - 2), tmp);
     /* cross products: c_j = f_j * b_{n-2-j} for j = 1..n-3; c_{n-2} = f_{n-2} * z_{i_n} */
     for (int j = 1; j <= n - 3; ++j)
-        conv(m, d, F(j), B(n - 2 - j), C(j), tmp);
-    conv(m, d, F(n - 2), ZS(I(n)), C(n - 2), tmp);
+        conv(m, cx, d, F(j), B(n - 2 - j), C(j), tmp);
+    conv(m, cx, d, F(n - 2), ZS(I(n)), C(n - 2), tmp);
     /* value f_n; d/dz_{i_1} = b_{n-2}; d/dz_{i_{j+1}} = c_j; d/dz_{i_n} = f_{n-1} */
     memcpy(val, F(n), sizeof(double) * S);
     memcpy(der[0], B(n - 2), sizeof(double) * S);
@@ -239,7 +293,7 @@ static void monomial(int m, int d, int nk, const int *v, const double *a, const 
  * the survivors are the odd-positioned elements plus a carried last element
  * when the count is odd.  The result ends in the last element of the list.
  */
-static void tree_sum(int m, int d, int len, double **items)
+static void tree_sum(int m, int cx, int d, int len, double **items)
 {
     int r = len;
     double **live = (double **)malloc(sizeof(double *) * (size_t)(len > 0 ? len : 1));
@@ -248,7 +302,7 @@ static void tree_sum(int m, int d, int len, double **items)
     while (r > 1) {
         int w = 0;
         for (int p = 0; p < r / 2; ++p) {
-            series_add(m, d, live[2 * p + 1], live[2 * p]);
+            series_add(m, cx, d, live[2 * p + 1], live[2 * p]);
             live[w++] = live[2 * p + 1];
         }
         if (r % 2)
@@ -310,18 +364,19 @@ static int check_support(int n, int N, const int *nvars, const int *vars)
 }
 
 /*
- * value [m][d+1], grad [m][n][d+1]; coeff [m][N+1][d+1] (a_0 first); z [m][n][d+1].
- * If monos is not NULL it receives, per monomial k, the value series
- * prod_j z_{i_j} * a_k (the forward product f_{k,n_k}) in planar [m][N][d+1].
+ * value [w][d+1], grad [w][n][d+1]; coeff [w][N+1][d+1] (a_0 first); z [w][n][d+1],
+ * with w = m planes of real limbs, or (cx = 1) w = 2m planes: the m real limbs,
+ * then the m imaginary limbs.
  * nthreads <= 0 leaves the OpenMP default.  Returns 0, or -1 on a bad support.
  */
-int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int *vars,
-                         const double *coeff, const double *z, double *value, double *grad,
-                         int nthreads)
+int oracle_eval_and_diff_field(int m, int cx, int d, int n, int N, const int *nvars, const int *vars,
+                               const double *coeff, const double *z, double *value, double *grad,
+                               int nthreads)
 {
-    if (m < 1 || m > MAXM || d < 0 || check_support(n, N, nvars, vars))
+    if (m < 1 || m > MAXM || cx < 0 || cx > 1 || d < 0 || check_support(n, N, nvars, vars))
         return -1;
-    const size_t S = (size_t)(d + 1) * m;
+    const int nl = m << cx; /* doubles per coefficient */
+    const size_t S = (size_t)(d + 1) * nl;
     size_t total = 0;
     size_t *start = (size_t *)malloc(sizeof(size_t) * (size_t)(N + 1));
     for (int k = 0; k < N; ++k) {
@@ -333,8 +388,8 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
     double *Z = (double *)malloc(sizeof(double) * S * (size_t)(n > 0 ? n : 1));
     double *vals = (double *)malloc(sizeof(double) * S * (size_t)(N + 1));
     double *ders = (double *)malloc(sizeof(double) * S * (total > 0 ? total : 1));
-    from_planar(m, d, N + 1, coeff, A);
-    from_planar(m, d, n, z, Z);
+    from_planar(nl, d, N + 1, coeff, A);
+    from_planar(nl, d, n, z, Z);
     /* value list starts with a_0 */
     memcpy(vals, A, sizeof(double) * S);
 #ifdef _OPENMP
@@ -354,7 +409,7 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
             int nk = nvars[k];
             for (int j = 0; j < nk; ++j)
                 der[j] = ders + (start[k] + (size_t)j) * S;
-            monomial(m, d, nk, vars + start[k], A + (size_t)(k + 1) * S, Z, vals + (size_t)(k + 1) * S, der,
+            monomial(m, cx, d, nk, vars + start[k], A + (size_t)(k + 1) * S, Z, vals + (size_t)(k + 1) * S, der,
                      work, work + S * (size_t)nmax, work + 2 * S * (size_t)nmax, work + 3 * S * (size_t)nmax);
         }
         free(work);
@@ -365,8 +420,8 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
         double **items = (double **)malloc(sizeof(double *) * (size_t)(N + 1));
         for (int k = 0; k <= N; ++k)
             items[k] = vals + (size_t)k * S;
-        tree_sum(m, d, N + 1, items);
-        to_planar(m, d, 1, 0, items[N], value);
+        tree_sum(m, cx, d, N + 1, items);
+        to_planar(nl, d, 1, 0, items[N], value);
         free(items);
     }
     /* gradient: list i holds the d/dz_i contributions in increasing monomial order */
@@ -378,7 +433,7 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
                 if (vars[start[k] + j] == i)
                     ++len;
         if (len == 0) {
-            for (int l = 0; l < m; ++l)
+            for (int l = 0; l < nl; ++l)
                 for (int c = 0; c <= d; ++c)
                     grad[((size_t)l * n + i) * (d + 1) + c] = 0.0;
             continue;
@@ -389,8 +444,8 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
             for (int j = 0; j < nvars[k]; ++j)
                 if (vars[start[k] + j] == i)
                     items[w++] = ders + (start[k] + (size_t)j) * S;
-        tree_sum(m, d, len, items);
-        to_planar(m, d, n, i, items[len - 1], grad);
+        tree_sum(m, cx, d, len, items);
+        to_planar(nl, d, n, i, items[len - 1], grad);
         free(items);
     }
     free(start);
@@ -399,6 +454,14 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
     free(vals);
     free(ders);
     return 0;
+}
+
+/* The real case: value [m][d+1], grad [m][n][d+1]; coeff [m][N+1][d+1]; z [m][n][d+1]. */
+int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int *vars,
+                         const double *coeff, const double *z, double *value, double *grad,
+                         int nthreads)
+{
+    return oracle_eval_and_diff_field(m, 0, d, n, N, nvars, vars, coeff, z, value, grad, nthreads);
 }
 
 /*
@@ -425,7 +488,7 @@ int oracle_monomial(int m, int d, int n, int nk, const int *v, const double *a /
     from_planar(m, d, n, z, Z);
     for (int j = 0; j < nk; ++j)
         der[j] = res + (size_t)(j + 1) * S;
-    monomial(m, d, nk, v, A, Z, res, der, work, work + S * (size_t)nk, work + 2 * S * (size_t)nk,
+    monomial(m, 0, d, nk, v, A, Z, res, der, work, work + S * (size_t)nk, work + 2 * S * (size_t)nk,
              work + 3 * S * (size_t)nk);
     for (int j = 0; j <= nk; ++j)
         to_planar(m, d, nk + 1, j, res + (size_t)j * S, out);
@@ -475,13 +538,13 @@ static void monomial_product(int m, int d, int nk, const int *v, const double *Z
         return;
     }
     if (nk == 2) {
-        conv(m, d, ZS(v[1]), ZS(v[0]), M, tmp);
+        conv(m, 0, d, ZS(v[1]), ZS(v[0]), M, tmp);
         return;
     }
-    conv(m, d, ZS(v[nk - 1]), ZS(v[nk - 2]), b, tmp);
+    conv(m, 0, d, ZS(v[nk - 1]), ZS(v[nk - 2]), b, tmp);
     for (int j = 2; j <= nk - 2; ++j)
-        conv(m, d, b, ZS(v[nk - 1 - j]), b, tmp);
-    conv(m, d, b, ZS(v[0]), M, tmp);
+        conv(m, 0, d, b, ZS(v[nk - 1 - j]), b, tmp);
+    conv(m, 0, d, b, ZS(v[0]), M, tmp);
 #undef ZS
 }
 
@@ -545,22 +608,24 @@ int oracle_eval_adjoint(int m, int d, int n, int N, const int *nvars, const int 
 }
 
 /* ---------------------------------------------- elementwise entry points -- */
-/* x, y, z planar [m][count]; op 0 = add, 1 = mul. */
+/* x, y, z planar [w][count]; op 0 = add, 1 = mul (w = m); op 2 = complex add,
+ * 3 = complex mul (w = 2m: real limbs, then imaginary limbs). */
 int oracle_md_op(int op, int m, long count, const double *x, const double *y, double *z)
 {
-    if (m < 1 || m > MAXM || count < 0 || op < 0 || op > 1)
+    if (m < 1 || m > MAXM || count < 0 || op < 0 || op > 3)
         return -1;
+    const int cx = op >= 2, w = m << cx;
     for (long i = 0; i < count; ++i) {
-        double a[MAXM], b[MAXM], r[MAXM];
-        for (int l = 0; l < m; ++l) {
+        double a[2 * MAXM], b[2 * MAXM], r[2 * MAXM];
+        for (int l = 0; l < w; ++l) {
             a[l] = x[(size_t)l * count + i];
             b[l] = y[(size_t)l * count + i];
         }
-        if (op == 0)
-            md_add(m, a, b, r);
+        if (op % 2 == 0)
+            coef_add(m, cx, a, b, r);
         else
-            md_mul(m, a, b, r);
-        for (int l = 0; l < m; ++l)
+            coef_mul(m, cx, a, b, r);
+        for (int l = 0; l < w; ++l)
             z[(size_t)l * count + i] = r[l];
     }
     return 0;
@@ -576,7 +641,7 @@ int oracle_conv(int m, int d, const double *x, const double *y, double *z)
     double *Zs = (double *)malloc(sizeof(double) * S), *T = (double *)malloc(sizeof(double) * S);
     from_planar(m, d, 1, x, X);
     from_planar(m, d, 1, y, Y);
-    conv(m, d, X, Y, Zs, T);
+    conv(m, 0, d, X, Y, Zs, T);
     to_planar(m, d, 1, 0, Zs, z);
     free(X);
     free(Y);

@@ -1,7 +1,9 @@
 """ctypes wrapper around oracle/liboracle.so (see oracle.c for what it computes).
 
 TEST INFRASTRUCTURE ONLY.  All arrays are float64 numpy arrays in the
-limb-planar layouts of the C file: series batches [m][count][d+1].
+limb-planar layouts of the C file: series batches [m][count][d+1]; complex
+data has a leading axis of two (real parts, then imaginary parts), which is
+the C file's 2m planes.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ def bind(path):
     """Load an oracle shared library from ``path`` and declare its signatures."""
     L = ctypes.CDLL(path)
     L.oracle_eval_and_diff.argtypes = [ctypes.c_int] * 4 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
+    L.oracle_eval_and_diff_field.argtypes = [ctypes.c_int] * 5 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
     L.oracle_monomial.argtypes = [ctypes.c_int] * 4 + [_ip, _dp, _dp, _dp]
     L.oracle_md_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
     L.oracle_conv.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
@@ -60,16 +63,20 @@ def _i32(a):
 
 
 def eval_and_diff(m, d, n, nvars, vars_, coeff, z, nthreads=0, L=None):
-    """Return (value [m][d+1], grad [m][n][d+1]).  ``L``: an alternative library from bind()."""
+    """Return (value [m][d+1], grad [m][n][d+1]); complex inputs ([2][m][...])
+    give complex outputs ([2][m][d+1], [2][m][n][d+1]).
+    ``L``: an alternative library from bind()."""
     nvars, vars_ = _i32(nvars), _i32(vars_)
     N = int(nvars.shape[0])
     coeff, z = _f64(coeff), _f64(z)
-    assert coeff.shape == (m, N + 1, d + 1), coeff.shape
-    assert z.shape == (m, n, d + 1), z.shape
-    value = np.empty((m, d + 1))
-    grad = np.empty((m, n, d + 1))
-    rc = (L or lib()).oracle_eval_and_diff(m, d, n, N, _i(nvars), _i(vars_), _d(coeff), _d(z), _d(value), _d(grad),
-                                    int(nthreads))
+    cx = coeff.ndim == 4
+    lead = (2, m) if cx else (m,)
+    assert coeff.shape == lead + (N + 1, d + 1), coeff.shape
+    assert z.shape == lead + (n, d + 1), z.shape
+    value = np.empty(lead + (d + 1,))
+    grad = np.empty(lead + (n, d + 1))
+    rc = (L or lib()).oracle_eval_and_diff_field(m, int(cx), d, n, N, _i(nvars), _i(vars_), _d(coeff), _d(z),
+                                                 _d(value), _d(grad), int(nthreads))
     if rc != 0:
         raise ValueError("oracle: invalid polynomial description")
     return value, grad
@@ -91,12 +98,15 @@ def monomial(m, d, n, v, a, z):
     return out
 
 
-def md_op(op, x, y):
-    """op 'add' or 'mul' on planar [m][count] arrays."""
+def md_op(op, x, y, L=None):
+    """op 'add' or 'mul' on planar [m][count] arrays; 'cadd' or 'cmul' on
+    complex [2][m][count] arrays."""
     x, y = _f64(x), _f64(y)
-    m, count = x.shape
+    code = {"add": 0, "mul": 1, "cadd": 2, "cmul": 3}[op]
+    m, count = x.shape[-2], x.shape[-1]
+    assert x.shape == y.shape and x.ndim == (3 if code >= 2 else 2)
     z = np.empty_like(x)
-    if lib().oracle_md_op({"add": 0, "mul": 1}[op], m, count, _d(x), _d(y), _d(z)) != 0:
+    if (L or lib()).oracle_md_op(code, m, count, _d(x), _d(y), _d(z)) != 0:
         raise ValueError("oracle: bad md op")
     return z
 

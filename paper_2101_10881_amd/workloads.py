@@ -10,6 +10,9 @@ Layouts (all C-contiguous float64 numpy arrays, limb 0 most significant):
 
 * ``coeff``: ``[m][N+1][d+1]`` -- a_0 first, then a_1..a_N (eq. (3) of the paper);
 * ``z``:     ``[m][n][d+1]``   -- the n input series z_1..z_n;
+* complex workloads carry a leading axis of two, real parts then imaginary
+  parts (``[2][m][N+1][d+1]`` and ``[2][m][n][d+1]``), the separate real and
+  imaginary arrays of Sections 2 and 5;
 * supports: ``nvars[N]`` (int32) and ``vars[sum nvars]`` (int32, 0-based,
   strictly increasing inside each monomial).
 
@@ -37,13 +40,18 @@ class Workload:
     n: int
     nvars: np.ndarray  # int32 [N]
     vars: np.ndarray   # int32 [sum nvars]
-    coeff: np.ndarray  # float64 [m][N+1][d+1]
-    z: np.ndarray      # float64 [m][n][d+1]
+    coeff: np.ndarray  # float64 [m][N+1][d+1], or [2][m][N+1][d+1] (complex)
+    z: np.ndarray      # float64 [m][n][d+1], or [2][m][n][d+1] (complex)
     meta: dict = field(default_factory=dict)
 
     @property
     def N(self) -> int:
         return int(self.nvars.shape[0])
+
+    @property
+    def cx(self) -> bool:
+        """Complex coefficients and inputs (real and imaginary parts)."""
+        return self.coeff.ndim == 4
 
     def supports(self):
         """List of tuples of 0-based variable indices, one per monomial."""
@@ -100,44 +108,57 @@ def all_subsets(n: int, r: int) -> list:
     return [tuple(c) for c in itertools.combinations(range(n), r)]
 
 
-def make(name: str, m: int, d: int, n: int, supports, seed: int = 1, meta=None) -> Workload:
-    """Build a workload from explicit supports: a_0..a_N first, then z_1..z_n."""
+def _draw_series(rng, N, n, m, d, cx):
+    """a_0..a_N, then z_1..z_n; complex: then the imaginary parts, in the same order."""
+    coeff = md_series(rng, N + 1, m, d)
+    z = md_series(rng, n, m, d)
+    if cx:
+        coeff = np.ascontiguousarray(np.stack([coeff, md_series(rng, N + 1, m, d)]))
+        z = np.ascontiguousarray(np.stack([z, md_series(rng, n, m, d)]))
+    return coeff, z
+
+
+def make(name: str, m: int, d: int, n: int, supports, seed: int = 1, meta=None, cx: bool = False) -> Workload:
+    """Build a workload from explicit supports: a_0..a_N first, then z_1..z_n
+    (complex: the real parts are those of the real workload with the same seed)."""
     if m not in SUPPORTED_M:
         raise ValueError(f"m={m} not in {SUPPORTED_M}")
     rng = np.random.default_rng(seed)
     nvars, vars_ = _pack_supports(supports)
-    coeff = md_series(rng, len(supports) + 1, m, d)
-    z = md_series(rng, n, m, d)
+    coeff, z = _draw_series(rng, len(supports), n, m, d, cx)
     return Workload(name, m, d, n, nvars, vars_, coeff, z, dict(meta or {}))
 
 
-def random_poly(name: str, m: int, d: int, n: int, N: int, nk, seed: int = 1) -> Workload:
+def random_poly(name: str, m: int, d: int, n: int, N: int, nk, seed: int = 1, cx: bool = False) -> Workload:
     """Supports drawn first from the same generator, then the series."""
     rng = np.random.default_rng(seed)
     if np.isscalar(nk):
         nk = [int(nk)] * N
     supports = random_supports(rng, n, N, nk)
     nvars, vars_ = _pack_supports(supports)
-    coeff = md_series(rng, N + 1, m, d)
-    z = md_series(rng, n, m, d)
+    coeff, z = _draw_series(rng, N, n, m, d, cx)
     return Workload(name, m, d, n, nvars, vars_, coeff, z, {"seed": seed})
 
 
 # ----- the five benchmark configurations ---------------------------------------------------
 
-def config0(seed: int = 1) -> Workload:
+def _cname(name, cx):
+    return name + "_complex" if cx else name
+
+
+def config0(seed: int = 1, cx: bool = False) -> Workload:
     """Double double, d=8: n=8, 16 monomials of 3 distinct variables each."""
-    return random_poly("c0_2d_d8_n8_N16", 2, 8, 8, 16, 3, seed)
+    return random_poly(_cname("c0_2d_d8_n8_N16", cx), 2, 8, 8, 16, 3, seed, cx)
 
 
-def config1(seed: int = 1, m: int = 10, d: int = 152) -> Workload:
+def config1(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
     """p1 (all 1820 4-subsets of 16 variables), deca double, d=152 (Table 3)."""
-    return make(f"c1_p1_{m}d_d{d}", m, d, 16, all_subsets(16, 4), seed, {"seed": seed})
+    return make(_cname(f"c1_p1_{m}d_d{d}", cx), m, d, 16, all_subsets(16, 4), seed, {"seed": seed}, cx)
 
 
-def config2(seed: int = 1, m: int = 4, d: int = 64) -> Workload:
+def config2(seed: int = 1, m: int = 4, d: int = 64, cx: bool = False) -> Workload:
     """p2 shape: n=128, 128 monomials of 64 distinct variables, quad double, d=64."""
-    return random_poly(f"c2_p2_{m}d_d{d}", m, d, 128, 128, 64, seed)
+    return random_poly(_cname(f"c2_p2_{m}d_d{d}", cx), m, d, 128, 128, 64, seed, cx)
 
 
 def config4(seed: int = 1) -> Workload:
@@ -145,9 +166,9 @@ def config4(seed: int = 1) -> Workload:
     return make("c4_p1_8d_d32", 8, 32, 16, all_subsets(16, 4), seed, {"seed": seed})
 
 
-def p3(seed: int = 1, m: int = 10, d: int = 152) -> Workload:
+def p3(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
     """p3: all 8128 products of two of 128 variables."""
-    return make(f"p3_{m}d_d{d}", m, d, 128, all_subsets(128, 2), seed, {"seed": seed})
+    return make(_cname(f"p3_{m}d_d{d}", cx), m, d, 128, all_subsets(128, 2), seed, {"seed": seed}, cx)
 
 
 def batch_instances(count: int = 512, seed: int = 1):

@@ -17,8 +17,53 @@ def md_value(limbs) -> Fraction:
     return sum((Fraction(float(v)) for v in limbs), Fraction(0))
 
 
+class CF:
+    """An exact complex rational re + im i (pairs of Fractions).  abs() is the
+    L1 modulus |re| + |im|, which bounds both parts of a product:
+    |re(xy)|, |im(xy)| <= abs(x) abs(y)."""
+
+    __slots__ = ("re", "im")
+
+    def __init__(self, re, im=Fraction(0)):
+        self.re, self.im = Fraction(re), Fraction(im)
+
+    @staticmethod
+    def _lift(v):
+        return v if isinstance(v, CF) else CF(v)
+
+    def __add__(self, o):
+        o = CF._lift(o)
+        return CF(self.re + o.re, self.im + o.im)
+
+    __radd__ = __add__
+
+    def __sub__(self, o):
+        o = CF._lift(o)
+        return CF(self.re - o.re, self.im - o.im)
+
+    def __mul__(self, o):
+        o = CF._lift(o)
+        return CF(self.re * o.re - self.im * o.im, self.re * o.im + self.im * o.re)
+
+    __rmul__ = __mul__
+
+    def __abs__(self):
+        return abs(self.re) + abs(self.im)
+
+    def __eq__(self, o):
+        o = CF._lift(o)
+        return self.re == o.re and self.im == o.im
+
+    def conj(self):
+        return CF(self.re, -self.im)
+
+
 def planar_to_exact(arr):
-    """[m][count][d+1] planar limbs -> list (count) of lists (d+1) of Fractions."""
+    """[m][count][d+1] planar limbs -> list (count) of lists (d+1) of Fractions;
+    complex [2][m][count][d+1] -> lists of CF."""
+    if arr.ndim == 4:
+        re, im = planar_to_exact(arr[0]), planar_to_exact(arr[1])
+        return [[CF(a, b) for a, b in zip(r, i)] for r, i in zip(re, im)]
     m, count, d1 = arr.shape
     return [[md_value(arr[:, s, c]) for c in range(d1)] for s in range(count)]
 
@@ -83,7 +128,12 @@ def bound(m: int, d: int) -> Fraction:
 
 
 def max_scaled_error(got_planar, exact, mag):
-    """max_k |got_k - exact_k| / mag_k over coefficients with mag_k > 0 (got: [m][d+1])."""
+    """max_k |got_k - exact_k| / mag_k over coefficients with mag_k > 0 (got: [m][d+1]);
+    complex got ([2][m][d+1]) against CF exact values: both parts, each against mag_k."""
+    if got_planar.ndim == 3:
+        exact = [CF._lift(e) for e in exact]
+        return max(max_scaled_error(got_planar[0], [e.re for e in exact], mag),
+                   max_scaled_error(got_planar[1], [e.im for e in exact], mag))
     worst = Fraction(0)
     for c in range(got_planar.shape[1]):
         g = md_value(got_planar[:, c])

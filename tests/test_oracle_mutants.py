@@ -4,7 +4,8 @@ rational pins reject it.  The mistakes cover a wrong variable index, a wrong
 backward-product index (including the literal index printed in Section 3's
 statement list, which the design reads as b_{n-2-j}), dropped terms in the
 multiple-double operations, a sign error in two_sum, a dropped carry in the
-addition tree and a mis-assigned partial derivative.
+addition tree, a mis-assigned partial derivative, and in the complex product
+a lost sign, a wrong cross term and a dropped imaginary sum.
 """
 import os
 import subprocess
@@ -18,14 +19,14 @@ from oracle import oracle as O
 from paper_2101_10881_amd import workloads as W
 
 MUTANTS = {
-    "forward_chain_wrong_variable": ("conv(m, d, F(j - 1), ZS(I(j)), F(j), tmp);",
-                                     "conv(m, d, F(j - 1), ZS(I(j - 1)), F(j), tmp);"),
-    "cross_product_literal_index": ("conv(m, d, F(j), B(n - 2 - j), C(j), tmp);",
-                                    "conv(m, d, F(j), B(n - 3 - j), C(j), tmp);"),
-    "cross_product_off_by_one": ("conv(m, d, F(j), B(n - 2 - j), C(j), tmp);",
-                                 "conv(m, d, F(j), B(n - 1 - j), C(j), tmp);"),
-    "backward_start_wrong": ("conv(m, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);",
-                             "conv(m, d, ZS(I(n)), ZS(I(n - 2)), B(1), tmp);"),
+    "forward_chain_wrong_variable": ("conv(m, cx, d, F(j - 1), ZS(I(j)), F(j), tmp);",
+                                     "conv(m, cx, d, F(j - 1), ZS(I(j - 1)), F(j), tmp);"),
+    "cross_product_literal_index": ("conv(m, cx, d, F(j), B(n - 2 - j), C(j), tmp);",
+                                    "conv(m, cx, d, F(j), B(n - 3 - j), C(j), tmp);"),
+    "cross_product_off_by_one": ("conv(m, cx, d, F(j), B(n - 2 - j), C(j), tmp);",
+                                 "conv(m, cx, d, F(j), B(n - 1 - j), C(j), tmp);"),
+    "backward_start_wrong": ("conv(m, cx, d, ZS(I(n)), ZS(I(n - 1)), B(1), tmp);",
+                             "conv(m, cx, d, ZS(I(n)), ZS(I(n - 2)), B(1), tmp);"),
     "md_add_drops_last_limb": ("for (int k = 0; k < m; ++k)\n        deposit(m, S, k, y[k]);",
                                "for (int k = 0; k < m - 1; ++k)\n        deposit(m, S, k, y[k]);"),
     "md_mul_drops_low_parts": ("deposit(m, S, k + 1, E[k]);", "(void)E[k];"),
@@ -33,10 +34,13 @@ MUTANTS = {
     "two_prod_no_error": ("*e = fma(a, b, -pp);", "*e = 0.0;"),
     "two_sum_sign": ("double err = (a - (ss - bb)) + (b - bb);", "double err = (a - (ss - bb)) - (b - bb);"),
     "renorm_skips_top_down": ("two_sum(e, u[j + 1], &r[j], &e);", "r[j] = u[j + 1];"),
-    "conv_skips_first_term": ("for (int i = 1; i <= k; ++i) {\n            md_mul(m, x + (size_t)i * m",
-                              "for (int i = 2; i <= k; ++i) {\n            md_mul(m, x + (size_t)i * m"),
+    "conv_skips_first_term": ("for (int i = 1; i <= k; ++i) {\n            coef_mul(m, cx, x + (size_t)i * w",
+                              "for (int i = 2; i <= k; ++i) {\n            coef_mul(m, cx, x + (size_t)i * w"),
     "tree_drops_carry": ("        if (r % 2)\n            live[w++] = live[r - 1];\n        r = w;\n    }\n    free(live);\n}\n\n/* The schedule",
                          "        r = w;\n    }\n    free(live);\n}\n\n/* The schedule"),
+    "complex_real_part_sign": ("ii[l] = -ii[l];", "ii[l] = ii[l];"),
+    "complex_cross_term_wrong": ("md_mul(m, x + m, y, ir);", "md_mul(m, x, y, ir);"),
+    "complex_add_drops_imaginary": ("md_add(m, x + m, y + m, z + m);", "memcpy(z + m, x + m, sizeof(double) * m);"),
     "last_partial_misassigned": ("memcpy(der[n - 1], F(n - 1), sizeof(double) * S);",
                                  "memcpy(der[n - 1], F(n - 2), sizeof(double) * S);"),
 }
@@ -54,6 +58,7 @@ def _pins_pass(L) -> bool:
             cases.append(W.random_poly("mut", m, int(rng.integers(1, 4)), n, N, nk, seed))
         cases.append(W.make("ex", m, 3, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4))
         cases.append(W.make("n5", m, 2, 7, [(0, 2, 3, 5, 6)], seed=9))
+        cases.append(W.make("ex_cx", m, 2, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4, cx=True))
     for w in cases:
         val, grad = O.eval_workload(w, L=L)
         (ev, eg), (mv, mg) = E.workload_exact(w)
@@ -61,7 +66,7 @@ def _pins_pass(L) -> bool:
         if E.max_scaled_error(val, ev, mv) > b:
             return False
         for i in range(w.n):
-            if E.max_scaled_error(grad[:, i, :], eg[i], mg[i]) > b:
+            if E.max_scaled_error(grad[..., i, :], eg[i], mg[i]) > b:
                 return False
     return True
 
