@@ -16,6 +16,9 @@
  *
  * Coefficients and inputs are real m-doubles, or complex ones whose real and
  * imaginary parts are kept apart (Sections 2 and 5); see cmd_mul below.
+ * Monomials may carry exponents: a_k prod z^e is the multilinear monomial with
+ * the common factor a_k prod z^(e-1) from a table of powers (Section 3), and
+ * each partial derivative is e times the multilinear one.
  *
  * Per monomial it runs the forward / backward / cross product recipe of
  * Section 3 (statement list and the n=5 example, eq. (2)), with the index
@@ -47,6 +50,7 @@
 #endif
 
 #define MAXM 10
+#define MAX_EXPONENT 64
 
 /* ---------------------------------------------------------------- md ops -- */
 
@@ -176,6 +180,17 @@ static void coef_add(int m, int cx, const double *x, const double *y, double *z)
         cmd_add(m, x, y, z);
     else
         md_add(m, x, y, z);
+}
+
+/* x := e * x for a small positive integer e: one md_mul by the m-double
+ * (e, 0, ..., 0); a complex x scales both parts. */
+static void coef_scale(int m, int cx, double *x, int e)
+{
+    double E[MAXM] = {0};
+    E[0] = (double)e;
+    md_mul(m, x, E, x);
+    if (cx)
+        md_mul(m, x + m, E, x + m);
 }
 
 /* ------------------------------------------------------------ series ops -- */
@@ -366,12 +381,13 @@ static int check_support(int n, int N, const int *nvars, const int *vars)
 /*
  * value [w][d+1], grad [w][n][d+1]; coeff [w][N+1][d+1] (a_0 first); z [w][n][d+1],
  * with w = m planes of real limbs, or (cx = 1) w = 2m planes: the m real limbs,
- * then the m imaginary limbs.
+ * then the m imaginary limbs.  exps: NULL (every exponent one), or [sum n_k]
+ * exponents 1..64 aligned with vars: monomial k is a_k prod_j z_{i_j}^{e_j}.
  * nthreads <= 0 leaves the OpenMP default.  Returns 0, or -1 on a bad support.
  */
-int oracle_eval_and_diff_field(int m, int cx, int d, int n, int N, const int *nvars, const int *vars,
-                               const double *coeff, const double *z, double *value, double *grad,
-                               int nthreads)
+int oracle_eval_and_diff_general(int m, int cx, int d, int n, int N, const int *nvars, const int *vars,
+                                 const int *exps, const double *coeff, const double *z, double *value,
+                                 double *grad, int nthreads)
 {
     if (m < 1 || m > MAXM || cx < 0 || cx > 1 || d < 0 || check_support(n, N, nvars, vars))
         return -1;
@@ -390,6 +406,43 @@ int oracle_eval_and_diff_field(int m, int cx, int d, int n, int N, const int *nv
     double *ders = (double *)malloc(sizeof(double) * S * (total > 0 ? total : 1));
     from_planar(nl, d, N + 1, coeff, A);
     from_planar(nl, d, n, z, Z);
+    for (size_t q = 0; exps && q < total; ++q)
+        if (exps[q] < 1 || exps[q] > MAX_EXPONENT) {
+            free(start);
+            free(A);
+            free(Z);
+            free(vals);
+            free(ders);
+            return -1;
+        }
+    /* Table of powers (Section 3, general exponents): P_i^1 = z_i and
+     * P_i^p = P_i^{p-1} * z_i up to the largest e - 1 over the occurrences of
+     * variable i; powoff[i] locates P_i^1, P_i^p follows at (p-1) series on. */
+    int *maxp = (int *)calloc((size_t)(n > 0 ? n : 1), sizeof(int));
+    size_t *powoff = (size_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(size_t));
+    size_t npow = 0;
+    for (size_t q = 0; q < total; ++q) {
+        int e = exps ? exps[q] : 1;
+        if (e - 1 > maxp[vars[q]])
+            maxp[vars[q]] = e - 1;
+    }
+    for (int i = 0; i < n; ++i) {
+        powoff[i] = npow;
+        npow += (size_t)maxp[i];
+    }
+    double *Pt = (double *)malloc(sizeof(double) * S * (npow > 0 ? npow : 1));
+    {
+        double *tmp = (double *)malloc(sizeof(double) * S);
+        for (int i = 0; i < n; ++i) {
+            if (maxp[i] == 0)
+                continue;
+            double *P1 = Pt + powoff[i] * S;
+            memcpy(P1, Z + (size_t)i * S, sizeof(double) * S);
+            for (int p = 2; p <= maxp[i]; ++p)
+                conv(m, cx, d, P1 + (size_t)(p - 2) * S, Z + (size_t)i * S, P1 + (size_t)(p - 1) * S, tmp);
+        }
+        free(tmp);
+    }
     /* value list starts with a_0 */
     memcpy(vals, A, sizeof(double) * S);
 #ifdef _OPENMP
@@ -402,15 +455,29 @@ int oracle_eval_and_diff_field(int m, int cx, int d, int n, int N, const int *nv
         for (int k = 0; k < N; ++k)
             if (nvars[k] > nmax)
                 nmax = nvars[k];
-        double *work = (double *)malloc(sizeof(double) * S * (size_t)(3 * nmax + 1));
+        double *work = (double *)malloc(sizeof(double) * S * (size_t)(3 * nmax + 2));
         double **der = (double **)malloc(sizeof(double *) * (size_t)nmax);
+        double *F = work + S * (size_t)(3 * nmax + 1);
 #pragma omp for schedule(dynamic, 1)
         for (int k = 0; k < N; ++k) {
             int nk = nvars[k];
+            const int *v = vars + start[k];
+            const int *e = exps ? exps + start[k] : NULL;
+            /* common factor F = a_k * prod_j z_{i_j}^{e_j - 1}, in increasing j
+               (a_k itself when every exponent is one) */
+            memcpy(F, A + (size_t)(k + 1) * S, sizeof(double) * S);
+            for (int j = 0; j < nk; ++j)
+                if (e && e[j] >= 2)
+                    conv(m, cx, d, F, Pt + (powoff[v[j]] + (size_t)(e[j] - 2)) * S, F, work + S * (size_t)(3 * nmax));
             for (int j = 0; j < nk; ++j)
                 der[j] = ders + (start[k] + (size_t)j) * S;
-            monomial(m, cx, d, nk, vars + start[k], A + (size_t)(k + 1) * S, Z, vals + (size_t)(k + 1) * S, der,
+            monomial(m, cx, d, nk, v, F, Z, vals + (size_t)(k + 1) * S, der,
                      work, work + S * (size_t)nmax, work + 2 * S * (size_t)nmax, work + 3 * S * (size_t)nmax);
+            /* d/dz_{i_j} of a z^e factor: e_j times the multilinear derivative */
+            for (int j = 0; j < nk; ++j)
+                if (e && e[j] >= 2)
+                    for (int c = 0; c <= d; ++c)
+                        coef_scale(m, cx, der[j] + (size_t)c * nl, e[j]);
         }
         free(work);
         free(der);
@@ -453,15 +520,18 @@ int oracle_eval_and_diff_field(int m, int cx, int d, int n, int N, const int *nv
     free(Z);
     free(vals);
     free(ders);
+    free(maxp);
+    free(powoff);
+    free(Pt);
     return 0;
 }
 
-/* The real case: value [m][d+1], grad [m][n][d+1]; coeff [m][N+1][d+1]; z [m][n][d+1]. */
+/* The multilinear real case: value [m][d+1], grad [m][n][d+1]; coeff [m][N+1][d+1]; z [m][n][d+1]. */
 int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int *vars,
                          const double *coeff, const double *z, double *value, double *grad,
                          int nthreads)
 {
-    return oracle_eval_and_diff_field(m, 0, d, n, N, nvars, vars, coeff, z, value, grad, nthreads);
+    return oracle_eval_and_diff_general(m, 0, d, n, N, nvars, vars, NULL, coeff, z, value, grad, nthreads);
 }
 
 /*

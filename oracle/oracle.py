@@ -24,7 +24,7 @@ def bind(path):
     """Load an oracle shared library from ``path`` and declare its signatures."""
     L = ctypes.CDLL(path)
     L.oracle_eval_and_diff.argtypes = [ctypes.c_int] * 4 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
-    L.oracle_eval_and_diff_field.argtypes = [ctypes.c_int] * 5 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
+    L.oracle_eval_and_diff_general.argtypes = [ctypes.c_int] * 5 + [_ip, _ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
     L.oracle_monomial.argtypes = [ctypes.c_int] * 4 + [_ip, _dp, _dp, _dp]
     L.oracle_md_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
     L.oracle_conv.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
@@ -62,9 +62,10 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-def eval_and_diff(m, d, n, nvars, vars_, coeff, z, nthreads=0, L=None):
+def eval_and_diff(m, d, n, nvars, vars_, coeff, z, nthreads=0, L=None, exps=None):
     """Return (value [m][d+1], grad [m][n][d+1]); complex inputs ([2][m][...])
-    give complex outputs ([2][m][d+1], [2][m][n][d+1]).
+    give complex outputs ([2][m][d+1], [2][m][n][d+1]).  exps: None (every
+    exponent one) or one exponent per entry of vars_.
     ``L``: an alternative library from bind()."""
     nvars, vars_ = _i32(nvars), _i32(vars_)
     N = int(nvars.shape[0])
@@ -73,17 +74,21 @@ def eval_and_diff(m, d, n, nvars, vars_, coeff, z, nthreads=0, L=None):
     lead = (2, m) if cx else (m,)
     assert coeff.shape == lead + (N + 1, d + 1), coeff.shape
     assert z.shape == lead + (n, d + 1), z.shape
+    if exps is not None:
+        exps = _i32(exps)
+        assert exps.shape == vars_.shape
     value = np.empty(lead + (d + 1,))
     grad = np.empty(lead + (n, d + 1))
-    rc = (L or lib()).oracle_eval_and_diff_field(m, int(cx), d, n, N, _i(nvars), _i(vars_), _d(coeff), _d(z),
-                                                 _d(value), _d(grad), int(nthreads))
+    rc = (L or lib()).oracle_eval_and_diff_general(m, int(cx), d, n, N, _i(nvars), _i(vars_),
+                                                   _i(exps) if exps is not None else None, _d(coeff), _d(z),
+                                                   _d(value), _d(grad), int(nthreads))
     if rc != 0:
         raise ValueError("oracle: invalid polynomial description")
     return value, grad
 
 
 def eval_workload(w, nthreads=0, L=None):
-    return eval_and_diff(w.m, w.d, w.n, w.nvars, w.vars, w.coeff, w.z, nthreads, L)
+    return eval_and_diff(w.m, w.d, w.n, w.nvars, w.vars, w.coeff, w.z, nthreads, L, getattr(w, "exps", None))
 
 
 def monomial(m, d, n, v, a, z):

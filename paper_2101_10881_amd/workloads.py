@@ -14,7 +14,9 @@ Layouts (all C-contiguous float64 numpy arrays, limb 0 most significant):
   parts (``[2][m][N+1][d+1]`` and ``[2][m][n][d+1]``), the separate real and
   imaginary arrays of Sections 2 and 5;
 * supports: ``nvars[N]`` (int32) and ``vars[sum nvars]`` (int32, 0-based,
-  strictly increasing inside each monomial).
+  strictly increasing inside each monomial);
+* ``exps``: None (every exponent one), or ``[sum nvars]`` int32 exponents
+  aligned with ``vars`` (monomial k is a_k prod_j z_{i_j}^{e_j}).
 
 The shapes follow the paper's test polynomials (Section 6.1, Table 2):
 p1 = all 1820 products of four of 16 variables; p2 = 128 monomials of 64 of
@@ -43,6 +45,7 @@ class Workload:
     coeff: np.ndarray  # float64 [m][N+1][d+1], or [2][m][N+1][d+1] (complex)
     z: np.ndarray      # float64 [m][n][d+1], or [2][m][n][d+1] (complex)
     meta: dict = field(default_factory=dict)
+    exps: np.ndarray = None  # int32 [sum nvars], or None: every exponent one
 
     @property
     def N(self) -> int:
@@ -141,6 +144,15 @@ def random_poly(name: str, m: int, d: int, n: int, N: int, nk, seed: int = 1, cx
 
 
 # ----- the five benchmark configurations ---------------------------------------------------
+
+def with_exponents(w: Workload, emax: int, seed: int = 1, frac: float = 0.5) -> Workload:
+    """The same workload with exponents: each occurrence of a variable gets,
+    with probability frac, an exponent drawn uniformly from 2..emax (else 1)."""
+    rng = np.random.default_rng(seed)
+    q = w.vars.shape[0]
+    e = np.where(rng.uniform(size=q) < frac, rng.integers(2, emax + 1, size=q), 1).astype(np.int32)
+    return Workload(w.name + f"_e{emax}", w.m, w.d, w.n, w.nvars, w.vars, w.coeff, w.z, dict(w.meta), e)
+
 
 def _cname(name, cx):
     return name + "_complex" if cx else name

@@ -83,10 +83,19 @@ def sadd(x, y):
     return [a + b for a, b in zip(x, y)]
 
 
-def poly_exact(supports, a, z):
-    """Exact value and gradient of p = a_0 + sum_k a_k prod_{j in S_k} z_j.
+def spow(x, e):
+    """x^e, truncated, by repeated products (e >= 0)."""
+    out = [Fraction(1)] + [Fraction(0)] * (len(x) - 1)
+    for _ in range(e):
+        out = smul(out, x)
+    return out
 
-    a: list of N+1 exact series (a_0 first); z: list of n exact series.
+
+def poly_exact(supports, a, z, exps=None):
+    """Exact value and gradient of p = a_0 + sum_k a_k prod_{j in S_k} z_j^{e_{k,j}}.
+
+    a: list of N+1 exact series (a_0 first); z: list of n exact series;
+    exps: None (every exponent one) or per monomial a tuple of exponents.
     Returns (value, [grad_0, ..., grad_{n-1}]).
     """
     d1 = len(a[0])
@@ -94,24 +103,24 @@ def poly_exact(supports, a, z):
     value = list(a[0])
     grad = [list(zero) for _ in z]
     for k, sup in enumerate(supports):
+        ek = exps[k] if exps is not None else (1,) * len(sup)
         term = list(a[k + 1])
-        for v in sup:
-            term = smul(term, z[v])
+        for v, e in zip(sup, ek):
+            term = smul(term, spow(z[v], e))
         value = sadd(value, term)
-        for i in sup:
-            g = list(a[k + 1])
-            for v in sup:
-                if v != i:
-                    g = smul(g, z[v])
+        for i, ei in zip(sup, ek):
+            g = [c * ei for c in a[k + 1]]
+            for v, e in zip(sup, ek):
+                g = smul(g, spow(z[v], e - 1 if v == i else e))
             grad[i] = sadd(grad[i], g)
     return value, grad
 
 
-def poly_magnitude(supports, a, z):
+def poly_magnitude(supports, a, z, exps=None):
     """The same computation on |coefficients|: the magnitude series used by the error bound."""
     aa = [[abs(c) for c in s] for s in a]
     zz = [[abs(c) for c in s] for s in z]
-    return poly_exact(supports, aa, zz)
+    return poly_exact(supports, aa, zz, exps)
 
 
 def workload_exact(w):
@@ -119,7 +128,13 @@ def workload_exact(w):
     a = planar_to_exact(w.coeff)
     z = planar_to_exact(w.z)
     sup = w.supports()
-    return poly_exact(sup, a, z), poly_magnitude(sup, a, z)
+    exps = None
+    if getattr(w, "exps", None) is not None:
+        exps, pos = [], 0
+        for s_ in sup:
+            exps.append(tuple(int(e) for e in w.exps[pos:pos + len(s_)]))
+            pos += len(s_)
+    return poly_exact(sup, a, z, exps), poly_magnitude(sup, a, z, exps)
 
 
 def bound(m: int, d: int) -> Fraction:

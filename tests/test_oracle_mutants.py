@@ -4,8 +4,10 @@ rational pins reject it.  The mistakes cover a wrong variable index, a wrong
 backward-product index (including the literal index printed in Section 3's
 statement list, which the design reads as b_{n-2-j}), dropped terms in the
 multiple-double operations, a sign error in two_sum, a dropped carry in the
-addition tree, a mis-assigned partial derivative, and in the complex product
-a lost sign, a wrong cross term and a dropped imaginary sum.
+addition tree, a mis-assigned partial derivative, in the complex product a
+lost sign, a wrong cross term and a dropped imaginary sum, and for general
+exponents a dropped or wrong exponent factor, a wrong power table and a
+skipped common factor.
 """
 import os
 import subprocess
@@ -41,6 +43,13 @@ MUTANTS = {
     "complex_real_part_sign": ("ii[l] = -ii[l];", "ii[l] = ii[l];"),
     "complex_cross_term_wrong": ("md_mul(m, x + m, y, ir);", "md_mul(m, x, y, ir);"),
     "complex_add_drops_imaginary": ("md_add(m, x + m, y + m, z + m);", "memcpy(z + m, x + m, sizeof(double) * m);"),
+    "exponent_scaling_dropped": ("coef_scale(m, cx, der[j] + (size_t)c * nl, e[j]);", "(void)c;"),
+    "exponent_scaling_off_by_one": ("coef_scale(m, cx, der[j] + (size_t)c * nl, e[j]);",
+                                    "coef_scale(m, cx, der[j] + (size_t)c * nl, e[j] - 1);"),
+    "power_table_wrong_base": ("conv(m, cx, d, P1 + (size_t)(p - 2) * S, Z + (size_t)i * S,",
+                               "conv(m, cx, d, P1, Z + (size_t)i * S,"),
+    "common_factor_skipped": ("conv(m, cx, d, F, Pt + (powoff[v[j]] + (size_t)(e[j] - 2)) * S, F,",
+                              "if (0) conv(m, cx, d, F, Pt + (powoff[v[j]] + (size_t)(e[j] - 2)) * S, F,"),
     "last_partial_misassigned": ("memcpy(der[n - 1], F(n - 1), sizeof(double) * S);",
                                  "memcpy(der[n - 1], F(n - 2), sizeof(double) * S);"),
 }
@@ -59,6 +68,9 @@ def _pins_pass(L) -> bool:
         cases.append(W.make("ex", m, 3, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4))
         cases.append(W.make("n5", m, 2, 7, [(0, 2, 3, 5, 6)], seed=9))
         cases.append(W.make("ex_cx", m, 2, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3)], seed=4, cx=True))
+        ex = W.make("ex_e", m, 3, 6, [(0, 2, 5), (0, 1, 4, 5), (1, 2, 3), (3,)], seed=6)
+        ex.exps = np.array([2, 1, 4, 1, 3, 1, 2, 5, 1, 1, 4], dtype=np.int32)
+        cases.append(ex)
     for w in cases:
         val, grad = O.eval_workload(w, L=L)
         (ev, eg), (mv, mg) = E.workload_exact(w)
