@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--polys", default="p1,p2,p3", help="sweep: test polynomials")
     ap.add_argument("--ms", default="1,2,3,4,5,8,10", help="sweep: precisions")
     ap.add_argument("--ds", default="0,8,15,31,63,95,127,152,159,191", help="sweep: degrees")
+    ap.add_argument("--complex", action="store_true", help="sweep: complex series")
     ap.add_argument("--instances", type=int, default=512, help="c3: number of instances")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-vs-plain (c3) and autograd (c4) side measurements")
@@ -213,9 +214,39 @@ def measure_c4(steps, warmup):
             "reverse_jobs": P.plan.info["n_reverse"], "forward_conv_jobs": P.plan.info["n_conv"]}
 
 
-def sweep_workload(poly, m, d):
+def measure_complex(steps, warmup, m=10, d=152):
+    """p1 with complex coefficients and inputs (real and imaginary parts in
+    separate limb planes), the headline precision and degree."""
+    import torch
+
+    from paper_2101_10881_amd import flops, mdpe
     from paper_2101_10881_amd import workloads as W
-    return {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d)
+
+    dev = torch.device("cuda", 0)
+    w = W.config1(m=m, d=d, cx=True)
+    P = mdpe.Polynomial.for_workload(w, dev)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    v, g = P.eval_and_diff(coeff, z)
+    for _ in range(warmup):
+        P.eval_and_diff(coeff, z, v, g)
+    torch.cuda.synchronize()
+    prof = mdpe.Profiler()
+    for _ in range(steps):
+        P.eval_and_diff(coeff, z, v, g, profiler=prof)
+    t = prof.read()
+    info = P.plan.info
+    cnv, add = t["cnv_ms"] / steps, t["add_ms"] / steps
+    conv_f = info["n_conv"] * flops.conv_flops(m, d, cx=True)
+    work = conv_f + info["n_add"] * flops.add_flops(m, d, cx=True)
+    return {"workload": w.name, "cnv_ms": round(cnv, 4), "add_ms": round(add, 4),
+            "GFLOPs": round(work / ((cnv + add) * 1e-3) / 1e9, 1),
+            "conv_TFLOPs": round(conv_f / (cnv * 1e-3) / 1e12, 3)}
+
+
+def sweep_workload(poly, m, d, cx=False):
+    from paper_2101_10881_amd import workloads as W
+    return {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
 
 
 def run_sweep(a):
@@ -231,7 +262,7 @@ def run_sweep(a):
     for poly in a.polys.split(","):
         for m in (int(x) for x in a.ms.split(",")):
             for d in (int(x) for x in a.ds.split(",")):
-                w = sweep_workload(poly, m, d)
+                w = sweep_workload(poly, m, d, a.complex)
                 P = mdpe.Polynomial.for_workload(w, dev)
                 coeff = torch.from_numpy(w.coeff).to(dev)
                 z = torch.from_numpy(w.z).to(dev)
@@ -246,8 +277,9 @@ def run_sweep(a):
                 wall = (time.perf_counter() - t0) * 1e3 / reps
                 t = prof.read()
                 info = P.plan.info
-                work = info["n_conv"] * flops.conv_flops(m, d) + info["n_add"] * flops.add_flops(m, d)
-                row = {"poly": poly, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
+                work = (info["n_conv"] * flops.conv_flops(m, d, a.complex)
+                        + info["n_add"] * flops.add_flops(m, d, a.complex))
+                row = {"poly": poly, "complex": a.complex, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
                        "add_ms": round(t["add_ms"] / reps, 4), "sum_ms": round((t["cnv_ms"] + t["add_ms"]) / reps, 4),
                        "wall_ms": round(wall, 4), "n_conv": info["n_conv"], "n_add": info["n_add"],
                        "TFLOPs": round(work / (t["cnv_ms"] + t["add_ms"]) * reps / 1e9, 3)}
@@ -377,6 +409,7 @@ def main():
     if not a.no_extras:
         out["batched_vs_plain"] = measure_c3(a.instances, 3, 1)
         out["autograd_c4"] = measure_c4(10, 2)
+        out["complex_p1"] = measure_complex(5, 1)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -53,7 +53,18 @@ typedef struct {
     const int32_t *nvars;   /* host [N]: n_k, 1 <= n_k <= n */
     const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
                                increasing inside each monomial (Section 4) */
-    uint32_t flags;         /* 0 or MDPE_KEEP_MONOMIAL_VALUES */
+    uint32_t flags;         /* 0, MDPE_KEEP_MONOMIAL_VALUES or MDPE_COMPLEX */
+    const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
+                               (every exponent one).  Monomial k is then
+                               a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
+                               multilinear monomial with the common factor
+                               a_k prod_j z_{i_j}^{e_j - 1}, taken from a table of
+                               powers z_i^p := z_i^{p-1} * z_i; the partial derivative
+                               for z_{i_j} is e_j times the multilinear one (an
+                               m-double product with (e_j, 0, ..., 0), per part when
+                               complex).  Not combinable with
+                               MDPE_KEEP_MONOMIAL_VALUES when an exponent exceeds one
+                               (MDPE_EUNSUPPORTED); plan_batch refuses such plans. */
 } mdpe_poly_desc;
 
 /* Plan flag: also compute and keep every monomial's product of variables
@@ -62,6 +73,17 @@ typedef struct {
  * gradient are bit-identical with or without it. */
 #define MDPE_KEEP_MONOMIAL_VALUES 1u
 
+/* Plan flag: complex series (Sections 2 and 5 keep real and imaginary parts in
+ * separate arrays).  Every coefficient, input and output buffer then holds
+ * 2m limb planes, the m real limbs followed by the m imaginary limbs, e.g.
+ * coeff double[2][m][N+1][d+1]; the workspace doubles.  A product of two
+ * complex m-doubles is (xr yr - xi yi) + (xr yi + xi yr) i with each product
+ * one m-double multiplication and each sum one m-double addition (the
+ * difference adds the exactly negated product); a sum adds the parts.
+ * Not combinable with MDPE_KEEP_MONOMIAL_VALUES (MDPE_EUNSUPPORTED), not
+ * accepted by plan_batch (MDPE_EUNSUPPORTED). */
+#define MDPE_COMPLEX 2u
+
 /* Plan summary. */
 typedef struct {
     int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
@@ -69,12 +91,14 @@ typedef struct {
     int64_t n_add;          /* addition jobs */
     int32_t n_layers;       /* convolution launches = largest n_k */
     int32_t n_levels;       /* addition launches */
-    int64_t workspace_bytes;/* device workspace eval_and_diff needs: n_series*(d+1)*m*8 */
+    int64_t workspace_bytes;/* device workspace eval_and_diff needs: n_series*(d+1)*m*8, twice that
+                               for MDPE_COMPLEX */
     int32_t jobs_per_group; /* convolution jobs per 64-lane workgroup */
     int32_t lane_steps;     /* multiply-add steps per lane per workgroup (lane schedule length) */
     int32_t n, N, d, m;
     int64_t n_reverse;      /* correlation jobs of the reverse pass (0 without the flag) */
     uint32_t flags;
+    int64_t n_scale;        /* exponent scale jobs (0 for multilinear polynomials) */
 } mdpe_plan_info;
 
 /*
@@ -108,19 +132,25 @@ int plan_add_jobs(const mdpe_plan *plan, int32_t *rows);
  * holding its partial derivative, or -1 when the variable is absent. */
 int plan_outputs(const mdpe_plan *plan, int32_t *out_slots);
 
+/* Exponent scale jobs as rows {src, dst, e}: A[dst] := e * A[src], coefficient
+ * by coefficient, after the last convolution layer and before the first
+ * addition level.  rows: int32[n_scale][3]. */
+int plan_scale_jobs(const mdpe_plan *plan, int32_t *rows);
+
 /*
  * Evaluate p and its gradient (Sections 4-5).
  *   coeff     device double[m][N+1][d+1], a_0 first (read only)
  *   z         device double[m][n][d+1] (read only)
  *   value     device double[m][d+1] (written)
  *   grad      device double[m][n][d+1] (written; absent variables get +0.0)
+ *   (MDPE_COMPLEX plans: each of these has a leading [2], real then imaginary)
  *   workspace device buffer of plan_info().workspace_bytes, 256-byte aligned;
  *             its contents are scratch and may be reused between calls
  *             that are ordered on one stream
  *   stream    hipStream_t or NULL
- * Launches: one staging kernel, one convolution kernel per layer, one
- * addition kernel per level, one gather kernel.  Calls on different streams
- * must not share a workspace.
+ * Launches: one staging kernel, one convolution kernel per layer, one scale
+ * kernel when an exponent exceeds one, one addition kernel per level, one
+ * gather kernel.  Calls on different streams must not share a workspace.
  */
 int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
                   double *grad, void *workspace, void *stream);
@@ -170,8 +200,10 @@ void profiler_destroy(mdpe_profiler *prof);
 
 /*
  * Elementwise m-double operation on device arrays (op 0: z = x + y,
- * op 1: z = x * y), planar double[m][count].  Diagnostic entry point that
- * exposes the device multiple-double library the kernels use.
+ * op 1: z = x * y), planar double[m][count]; complex m-doubles (op 2: z = x + y,
+ * op 3: z = x * y), planar double[2][m][count], real limbs then imaginary limbs.
+ * Diagnostic entry point that exposes the device multiple-double library the
+ * kernels use.
  */
 int md_elementwise(int op, int m, int64_t count, const double *x, const double *y, double *z, void *stream);
 

@@ -280,6 +280,8 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         int dev = plans[p]->device;
         if (p == 0) B->device = dev;
         if (dev != B->device) return bfail(MDPE_EINVAL, "plans on different devices (or host-only mixed in)");
+        if (P->complex_series()) return bfail(MDPE_EUNSUPPORTED, "batches hold real series only (MDPE_COMPLEX plan)");
+        if (!P->scale.empty()) return bfail(MDPE_EUNSUPPORTED, "batches hold multilinear polynomials only (exponents)");
         if (std::find(ms.begin(), ms.end(), P->m) == ms.end()) ms.push_back(P->m);
     }
     std::sort(ms.begin(), ms.end());

@@ -30,7 +30,7 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
     st.i = 0;
 }
 
-// LDS layout of one workgroup: X[J][d+1][M] doubles (the first operands),
+// LDS layout of one workgroup: X[J][d+1][W] doubles (the first operands),
 // then the J job descriptors (16-byte aligned).
 __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
 
@@ -38,22 +38,25 @@ __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xd
 // CORR = true:  correlation z_s = sum_{j=0..d-s} x_{s+j} y_j (the reverse pass);
 //               chain code k then denotes s = d-k, with k+1 terms, x index d-k+i
 //               and y index i, so the same lane schedule balances both.
+// CX = true: complex series, W = 2M doubles per coefficient (cmd_mul, cmd_add).
 // One 64-lane wavefront computes jn <= J jobs jobs[0..jn) (the output
 // coefficients of each spread over the lanes by the schedule `chains`).
-// lds must hold conv_lds_jobs_offset(J*(d+1)*M) + J*16 bytes.  Ends with the
+// lds must hold conv_lds_jobs_offset(J*(d+1)*W) + J*16 bytes.  Ends with the
 // wavefront's stores issued (not necessarily complete).
-template <int M, bool CORR>
+template <int M, bool CORR, bool CX = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
                                            int steps, int lane) {
-    const long S = (long)(d + 1) * M;
+    constexpr int W = kCoef<M, CX>;
+    const long S = (long)(d + 1) * W;
     double *X = lds;
     int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * S));
     // Stage the first operand of every job in LDS: it is read by all lanes and
     // may be the job's own output (the in-place b := b * a of Section 3).  The
     // second operand is never the output (the planner checks) and is streamed
     // from global memory -- mostly one of the shared input series, so it stays
-    // in L2.  Both operands are fetched one step ahead of their use.
+    // in L2.  The first operand is read from LDS one step ahead of its use,
+    // the second from global memory two steps ahead.
     for (int j = 0; j < jn; ++j) {
         const int4 t = jobs[j];
         const double *xs = A + (long)t.x * S;
@@ -63,93 +66,115 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     __syncthreads();
 
     const int *my = chains + (long)lane * stride;
+    // Next position in the lane's chain list (reads the -1 terminator at most).
+    auto advance = [&](const ChainState &cur, ChainState &nxt, int4 &nj) {
+        nxt = cur;
+        if (cur.i == cur.k) {
+            if (cur.code >= 0) nxt.code = my[++nxt.c];
+            chain_decode(nxt, jn);
+            if (nxt.live) nj = jd[nxt.j];
+        } else {
+            nxt.i = cur.i + 1;
+        }
+    };
+    auto xidx = [&](int k, int i) { return CORR ? d - k + i : i; };
+    auto yidx = [&](int k, int i) { return CORR ? i : k - i; };
+
+    // Software pipeline over the lane's steps: iteration s accumulates the
+    // product of step s while it computes the product of step s+1 (the two are
+    // independent, and sit in one basic block so the scheduler can interleave
+    // them) and loads the second operand of step s+2.
     ChainState st;
     st.c = 0;
     st.code = my[0];
     chain_decode(st, jn);
     int4 job = jd[st.live ? st.j : 0];
-    auto xidx = [&](int k, int i) { return CORR ? d - k + i : i; };
-    auto yidx = [&](int k, int i) { return CORR ? i : k - i; };
-    double xc[M], yc[M];
+    double p[W];
     {
-        const double *xp = X + st.j * S + xidx(st.k, 0) * M;
-        const double *yp = A + (long)job.y * S + (long)yidx(st.k, 0) * M;
+        const double *xp = X + st.j * S + xidx(st.k, 0) * W;
+        const double *yp = A + (long)job.y * S + (long)yidx(st.k, 0) * W;
+        double x0[W], y0[W];
 #pragma unroll
-        for (int l = 0; l < M; ++l) {
-            xc[l] = xp[l];
-            yc[l] = st.live ? yp[l] : 0.0;
+        for (int l = 0; l < W; ++l) {
+            x0[l] = xp[l];
+            y0[l] = st.live ? yp[l] : 0.0;
         }
+        coef_mul<M, CX>(x0, y0, p);
     }
-    double acc[M];
+    ChainState nx;
+    int4 njob = job;
+    advance(st, nx, njob);
+    double yn[W];
+    {
+        const double *yp = A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * W;
+        const bool fetch = nx.live && 1 < steps;
+#pragma unroll
+        for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
+    }
+    double acc[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) acc[l] = 0.0;
     for (int s = 0; s < steps; ++s) {
-        // next position, and the prefetch of its operands
-        ChainState nx = st;
-        int4 njob = job;
-        if (st.i == st.k) {
-            if (st.code >= 0) nx.code = my[++nx.c];
-            chain_decode(nx, jn);
-            if (nx.live) njob = jd[nx.j];
-        } else {
-            nx.i = st.i + 1;
-        }
-        double xn[M], yn[M];
+        ChainState n2;
+        int4 n2job = njob;
+        advance(nx, n2, n2job);
+        double x1[W], y1[W];
+#pragma unroll
+        for (int l = 0; l < W; ++l) y1[l] = yn[l];
         {
-            const bool fetch = nx.live && s + 1 < steps;
-            const double *xp = X + nx.j * S + xidx(nx.k, nx.i) * M;
-            const double *yp = A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * M;
+            const double *xp = X + nx.j * S + xidx(nx.k, nx.i) * W;
 #pragma unroll
-            for (int l = 0; l < M; ++l) {
-                xn[l] = xp[l];
-                yn[l] = fetch ? yp[l] : 0.0;
-            }
-        }
-        double p[M];
-        md_mul<M>(xc, yc, p);
-        if (st.i == 0) {
+            for (int l = 0; l < W; ++l) x1[l] = xp[l];
+            const bool fetch = n2.live && s + 2 < steps;
+            const double *yp = A + (long)n2job.y * S + (long)yidx(n2.k, n2.i) * W;
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc[l] = p[l];
-        } else {
-            md_add<M>(acc, p, acc);
+            for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
         }
+        double pn[W], r[W];
+        coef_mul<M, CX>(x1, y1, pn);   // step s+1 (unused past the lane's last step)
+        coef_add<M, CX>(acc, p, r);    // step s; a chain's first term replaces acc
+        const bool first = st.i == 0;
+#pragma unroll
+        for (int l = 0; l < W; ++l) acc[l] = first ? p[l] : r[l];
         if (st.i == st.k && st.live) {
-            double *out = A + (long)job.z * S + (long)(CORR ? d - st.k : st.k) * M;
+            double *out = A + (long)job.z * S + (long)(CORR ? d - st.k : st.k) * W;
 #pragma unroll
-            for (int l = 0; l < M; ++l) out[l] = acc[l];
+            for (int l = 0; l < W; ++l) out[l] = acc[l];
         }
         st = nx;
         job = njob;
+        nx = n2;
+        njob = n2job;
 #pragma unroll
-        for (int l = 0; l < M; ++l) {
-            xc[l] = xn[l];
-            yc[l] = yn[l];
-        }
+        for (int l = 0; l < W; ++l) p[l] = pn[l];
     }
 }
 
-template <int M, bool CORR>
+template <int M, bool CORR, bool CX = false>
 __global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                         int njobs, int d, int J, const int *__restrict__ chains,
                                                         int stride, int steps) {
     extern __shared__ double lds[];
     const int g0 = blockIdx.x * J;
-    conv_group<M, CORR>(A, jobs + g0, min(J, njobs - g0), J, d, lds, chains, stride, steps, threadIdx.x);
+    conv_group<M, CORR, CX>(A, jobs + g0, min(J, njobs - g0), J, d, lds, chains, stride, steps, threadIdx.x);
 }
 
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).
-template <int M>
+template <int M, bool CX = false>
 __device__ __forceinline__ void add_item(double *__restrict__ A, int2 t, int c, int d) {
-    const long S = (long)(d + 1) * M;
-    double *up = A + (long)t.y * S + (long)c * M;
-    const double *in = A + (long)t.x * S + (long)c * M;
-    double x[M], y[M], z[M];
+    constexpr int W = kCoef<M, CX>;
+    const long S = (long)(d + 1) * W;
+    double *up = A + (long)t.y * S + (long)c * W;
+    const double *in = A + (long)t.x * S + (long)c * W;
+    double x[W], y[W], z[W];
 #pragma unroll
-    for (int l = 0; l < M; ++l) {
+    for (int l = 0; l < W; ++l) {
         x[l] = up[l];
         y[l] = in[l];
     }
-    md_add<M>(x, y, z);
+    coef_add<M, CX>(x, y, z);
 #pragma unroll
-    for (int l = 0; l < M; ++l) up[l] = z[l];
+    for (int l = 0; l < W; ++l) up[l] = z[l];
 }
 
 // user coefficient / input series -> staged slot (entry (slot, source) at coefficient c)

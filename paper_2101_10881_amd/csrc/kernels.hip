@@ -37,7 +37,7 @@ namespace mdpe {
 
 // ------------------------------------------------------------------ kernels
 
-template <int M>
+template <int M, bool CX>
 __global__ __launch_bounds__(256) void add_level_kernel(double *__restrict__ A, const int2 *__restrict__ pairs,
                                                         long total, int d) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -45,7 +45,35 @@ __global__ __launch_bounds__(256) void add_level_kernel(double *__restrict__ A, 
     const int d1 = d + 1;
     const long p = idx / d1;
     const int c = (int)(idx - p * d1);
-    add_item<M>(A, pairs[p], c, d);
+    add_item<M, CX>(A, pairs[p], c, d);
+}
+
+// A[dst] := e * A[src] at every coefficient of every scale job: one md_mul by
+// (e, 0, ..., 0) per part (general exponents, Section 3).
+template <int M, bool CX>
+__global__ __launch_bounds__(256) void scale_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                    long total, int d) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    constexpr int W = kCoef<M, CX>;
+    const int d1 = d + 1;
+    const long q = idx / d1;
+    const int c = (int)(idx - q * d1);
+    const int4 t = jobs[q];
+    const long S = (long)d1 * W;
+    const double *in = A + (long)t.x * S + (long)c * W;
+    double *out = A + (long)t.y * S + (long)c * W;
+    double E[M], x[M], r[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) E[l] = l == 0 ? (double)t.z : 0.0;
+#pragma unroll
+    for (int part = 0; part < (CX ? 2 : 1); ++part) {
+#pragma unroll
+        for (int l = 0; l < M; ++l) x[l] = in[part * M + l];
+        md_mul<M>(x, E, r);
+#pragma unroll
+        for (int l = 0; l < M; ++l) out[part * M + l] = r[l];
+    }
 }
 
 __global__ __launch_bounds__(256) void stage_kernel(double *__restrict__ A, const double *__restrict__ coeff,
@@ -96,23 +124,25 @@ __global__ __launch_bounds__(256) void slots_to_planar_kernel(const double *__re
         dst[((long)l * count + e) * d1 + c] = slot >= 0 ? A[(long)slot * d1 * m + (long)c * m + l] : 0.0;
 }
 
-template <int M>
+// op 0 / 1: md_add / md_mul on planar [M][count]; CX: cmd_add / cmd_mul on [2M][count]
+template <int M, bool CX>
 __global__ __launch_bounds__(256) void md_elementwise_kernel(int op, long count, const double *__restrict__ x,
                                                              const double *__restrict__ y, double *__restrict__ z) {
+    constexpr int W = kCoef<M, CX>;
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
-    double a[M], b[M], r[M];
+    double a[W], b[W], r[W];
 #pragma unroll
-    for (int l = 0; l < M; ++l) {
+    for (int l = 0; l < W; ++l) {
         a[l] = x[(long)l * count + i];
         b[l] = y[(long)l * count + i];
     }
     if (op == 0)
-        md_add<M>(a, b, r);
+        coef_add<M, CX>(a, b, r);
     else
-        md_mul<M>(a, b, r);
+        coef_mul<M, CX>(a, b, r);
 #pragma unroll
-    for (int l = 0; l < M; ++l) z[(long)l * count + i] = r[l];
+    for (int l = 0; l < W; ++l) z[(long)l * count + i] = r[l];
 }
 
 }  // namespace mdpe
@@ -182,6 +212,7 @@ void free_plan(mdpe_plan *p) {
         (void)hipFree(p->d_cbar);
         (void)hipFree(p->d_zbar);
         (void)hipFree(p->d_ybar);
+        (void)hipFree(p->d_scale);
     }
     delete p;
 }
@@ -218,14 +249,14 @@ int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
         if (e_ != hipSuccess) return fail(MDPE_EDEVICE, std::string(what ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-template <int M, bool CORR>
+template <int M, bool CORR, bool CX>
 int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
-    const size_t lds = conv_lds_bytes(P.d, M, J, P.lanes.stride);
+    const size_t lds = conv_lds_bytes(P.d, mdpe::kCoef<M, CX>, J, P.lanes.stride);
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR>,
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set = true;
     }
@@ -233,24 +264,24 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
     const int groups = (nj + J - 1) / J;
     int rc = record(prof, 1, st, true);
     if (rc) return rc;
-    hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR>), dim3(groups), dim3(64), lds, st, A, jobs, nj, P.d, J,
+    hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX>), dim3(groups), dim3(64), lds, st, A, jobs, nj, P.d, J,
                        pl->d_chains, P.lanes.stride, P.lanes.steps);
     LAUNCH_CHECK("conv_layer_kernel");
     return record(prof, 1, st, false);
 }
 
-template <int M>
+template <int M, bool CX>
 int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     for (int L = 1; L <= P.n_layers(); ++L) {
         const long off = P.conv_off[L - 1];
-        int rc = launch_layer<M, false>(pl, A, pl->d_conv + off, (int)(P.conv_off[L] - off), st, prof);
+        int rc = launch_layer<M, false, CX>(pl, A, pl->d_conv + off, (int)(P.conv_off[L] - off), st, prof);
         if (rc) return rc;
     }
     return MDPE_OK;
 }
 
-template <int M>
+template <int M, bool CX>
 int launch_add(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     for (int r = 1; r <= P.n_levels(); ++r) {
@@ -260,7 +291,7 @@ int launch_add(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *pr
         const long total = np * (P.d + 1);
         int rc = record(prof, 2, st, true);
         if (rc) return rc;
-        hipLaunchKernelGGL(mdpe::add_level_kernel<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A,
+        hipLaunchKernelGGL((mdpe::add_level_kernel<M, CX>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A,
                            pl->d_add + off, total, P.d);
         LAUNCH_CHECK("add_level_kernel");
         if ((rc = record(prof, 2, st, false))) return rc;
@@ -268,11 +299,30 @@ int launch_add(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *pr
     return MDPE_OK;
 }
 
+template <int M, bool CX>
+int launch_scale(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    if (P.scale.empty()) return MDPE_OK;
+    const long total = (long)P.scale.size() * (P.d + 1);
+    int rc = record(prof, 2, st, true);
+    if (rc) return rc;
+    hipLaunchKernelGGL((mdpe::scale_kernel<M, CX>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A,
+                       pl->d_scale, total, P.d);
+    LAUNCH_CHECK("scale_kernel");
+    return record(prof, 2, st, false);
+}
+
+template <int M, bool CX>
+int run_field(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    int rc;
+    if ((rc = launch_conv<M, CX>(pl, A, st, prof))) return rc;
+    if ((rc = launch_scale<M, CX>(pl, A, st, prof))) return rc;
+    return launch_add<M, CX>(pl, A, st, prof);
+}
+
 template <int M>
 int run_md(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
-    int rc = launch_conv<M>(pl, A, st, prof);
-    if (rc) return rc;
-    return launch_add<M>(pl, A, st, prof);
+    return pl->P.complex_series() ? run_field<M, true>(pl, A, st, prof) : run_field<M, false>(pl, A, st, prof);
 }
 
 int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
@@ -293,7 +343,7 @@ int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double 
         const long total = (long)P.stage.size() * d1;
         if ((rc = record(prof, 0, st, true))) return rc;
         hipLaunchKernelGGL(mdpe::stage_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, coeff, z,
-                           pl->d_stage, total, P.N, P.n, P.d, P.m);
+                           pl->d_stage, total, P.N, P.n, P.d, P.w);
         LAUNCH_CHECK("stage_kernel");
         if ((rc = record(prof, 0, st, false))) return rc;
     }
@@ -312,7 +362,7 @@ int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double 
         const long total = (long)(1 + P.n) * d1;
         if ((rc = record(prof, 3, st, true))) return rc;
         hipLaunchKernelGGL(mdpe::gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, value,
-                           grad, pl->d_out, P.n, P.d, P.m);
+                           grad, pl->d_out, P.n, P.d, P.w);
         LAUNCH_CHECK("gather_kernel");
         if ((rc = record(prof, 3, st, false))) return rc;
     }
@@ -341,13 +391,13 @@ int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, doubl
     if ((rc = record(prof, 0, st, false))) return rc;
     const int nj = (int)P.corr.size();
     switch (P.m) {
-        case 1: rc = launch_layer<1, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 2: rc = launch_layer<2, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 3: rc = launch_layer<3, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 4: rc = launch_layer<4, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 5: rc = launch_layer<5, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 8: rc = launch_layer<8, true>(pl, A, pl->d_corr, nj, st, prof); break;
-        case 10: rc = launch_layer<10, true>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 1: rc = launch_layer<1, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 2: rc = launch_layer<2, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 3: rc = launch_layer<3, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 4: rc = launch_layer<4, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 5: rc = launch_layer<5, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 8: rc = launch_layer<8, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
+        case 10: rc = launch_layer<10, true, false>(pl, A, pl->d_corr, nj, st, prof); break;
         default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
     }
     if (rc) return rc;
@@ -364,6 +414,15 @@ int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, doubl
     return record(prof, 3, st, false);
 }
 
+template <int M>
+void launch_elementwise(int op, long count, const double *x, const double *y, double *z, hipStream_t st) {
+    const dim3 grid((unsigned)((count + 255) / 256));
+    if (op >= 2)
+        hipLaunchKernelGGL((mdpe::md_elementwise_kernel<M, true>), grid, dim3(256), 0, st, op - 2, count, x, y, z);
+    else
+        hipLaunchKernelGGL((mdpe::md_elementwise_kernel<M, false>), grid, dim3(256), 0, st, op, count, x, y, z);
+}
+
 }  // namespace
 
 extern "C" {
@@ -371,14 +430,14 @@ extern "C" {
 int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
-    if (desc->flags & ~(uint32_t)MDPE_KEEP_MONOMIAL_VALUES) return fail(MDPE_EINVAL, "unknown flags");
+    if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX)) return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
     if (!pl) return fail(MDPE_ENOMEM, "host allocation failed");
     bool unsupported = false;
     std::string err;
     try {
-        err = mdpe::build_plan(desc->n, desc->N, desc->d, desc->m, desc->nvars, desc->vars, desc->flags, pl->P,
+        err = mdpe::build_plan(desc->n, desc->N, desc->d, desc->m, desc->nvars, desc->vars, desc->exps, desc->flags, pl->P,
                                &unsupported);
     } catch (const std::bad_alloc &) {
         return fail(MDPE_ENOMEM, "host allocation failed while planning");
@@ -396,6 +455,8 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
         for (size_t q = 0; q < P.conv.size(); ++q) conv[q] = make_int4(P.conv[q][0], P.conv[q][1], P.conv[q][2], 0);
         std::vector<int4> corr(P.corr.size());
         for (size_t q = 0; q < P.corr.size(); ++q) corr[q] = make_int4(P.corr[q][0], P.corr[q][1], P.corr[q][2], 0);
+        std::vector<int4> scale(P.scale.size());
+        for (size_t q = 0; q < P.scale.size(); ++q) scale[q] = make_int4(P.scale[q][0], P.scale[q][1], P.scale[q][2], 0);
         std::vector<int2> add(P.add.size()), stage(P.stage.size());
         for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
         for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
@@ -409,7 +470,8 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
             (rc = upload(&raw->d_corr, corr.data(), corr.size() * sizeof(int4))) ||
             (rc = upload(&raw->d_cbar, P.coeff_bar_slots.data(), P.coeff_bar_slots.size() * sizeof(int))) ||
             (rc = upload(&raw->d_zbar, P.z_bar_slots.data(), P.z_bar_slots.size() * sizeof(int))) ||
-            (rc = upload(&raw->d_ybar, &P.ybar_slot, sizeof(int)))) {
+            (rc = upload(&raw->d_ybar, &P.ybar_slot, sizeof(int))) ||
+            (rc = upload(&raw->d_scale, scale.data(), scale.size() * sizeof(int4)))) {
             std::string keep = g_err;
             free_plan(pl.release());
             g_err = keep;
@@ -428,10 +490,11 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->n_add = (int64_t)P.add.size();
     o->n_layers = P.n_layers();
     o->n_levels = P.n_levels();
-    o->workspace_bytes = P.n_series * (int64_t)(P.d + 1) * P.m * (int64_t)sizeof(double);
+    o->workspace_bytes = P.n_series * (int64_t)(P.d + 1) * P.w * (int64_t)sizeof(double);
     o->jobs_per_group = P.lanes.jobs_per_group;
     o->lane_steps = P.lanes.steps;
     o->n_reverse = (int64_t)P.corr.size();
+    o->n_scale = (int64_t)P.scale.size();
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;
@@ -481,6 +544,14 @@ int plan_outputs(const mdpe_plan *pl, int32_t *out_slots) {
     return MDPE_OK;
 }
 
+int plan_scale_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    for (size_t q = 0; q < P.scale.size(); ++q)
+        for (int r = 0; r < 3; ++r) rows[3 * q + r] = P.scale[q][r];
+    return MDPE_OK;
+}
+
 int eval_and_diff(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
                   void *workspace, void *stream) {
     return eval_impl(pl, coeff, z, value, grad, workspace, stream, nullptr);
@@ -526,20 +597,19 @@ void profiler_destroy(mdpe_profiler *prof) {
 }
 
 int md_elementwise(int op, int m, int64_t count, const double *x, const double *y, double *z, void *stream) {
-    if (op < 0 || op > 1) return fail(MDPE_EINVAL, "op must be 0 (add) or 1 (mul)");
+    if (op < 0 || op > 3) return fail(MDPE_EINVAL, "op must be 0 (add), 1 (mul), 2 (complex add) or 3 (complex mul)");
     if (count < 0) return fail(MDPE_EINVAL, "count < 0");
     if (count == 0) return MDPE_OK;
     if (!x || !y || !z) return fail(MDPE_EINVAL, "NULL buffer");
     hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)((count + 255) / 256));
     switch (m) {
-        case 1: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<1>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 2: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<2>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 3: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<3>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 4: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<4>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 5: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<5>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 8: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<8>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
-        case 10: hipLaunchKernelGGL(mdpe::md_elementwise_kernel<10>, grid, dim3(256), 0, st, op, (long)count, x, y, z); break;
+        case 1: launch_elementwise<1>(op, (long)count, x, y, z, st); break;
+        case 2: launch_elementwise<2>(op, (long)count, x, y, z, st); break;
+        case 3: launch_elementwise<3>(op, (long)count, x, y, z, st); break;
+        case 4: launch_elementwise<4>(op, (long)count, x, y, z, st); break;
+        case 5: launch_elementwise<5>(op, (long)count, x, y, z, st); break;
+        case 8: launch_elementwise<8>(op, (long)count, x, y, z, st); break;
+        case 10: launch_elementwise<10>(op, (long)count, x, y, z, st); break;
         default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
     }
     LAUNCH_CHECK("md_elementwise_kernel");

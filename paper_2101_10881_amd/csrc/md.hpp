@@ -16,6 +16,12 @@
 //   md_add(x, y)    S = x; deposit y_k at level k; renorm
 //   md_mul(x, y)    exact products of levels 0..M-2, plain FMAs for levels
 //                   M-1 and M, exact low parts pushed one level down; renorm
+//
+// Complex m-doubles (real and imaginary parts kept apart, Sections 2 and 5)
+// are 2M doubles, the real limbs then the imaginary ones:
+//   cmd_mul(x, y)   re = md_add(xr*yr, -(xi*yi)), im = md_add(xr*yi, xi*yr),
+//                   each product an md_mul, the negation exact
+//   cmd_add(x, y)   md_add of the real parts and of the imaginary parts
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -120,6 +126,73 @@ __device__ __forceinline__ void md_mul(const double (&x)[M], const double (&y)[M
         });
     });
     renorm<M>(S, z);
+}
+
+// Doubles per coefficient: M limbs, or 2M for complex series.
+template <int M, bool CX>
+constexpr int kCoef = CX ? 2 * M : M;
+
+template <int M>
+__device__ __forceinline__ void cmd_mul(const double (&x)[2 * M], const double (&y)[2 * M], double (&z)[2 * M]) {
+    double xr[M], xi[M], yr[M], yi[M];
+    sfor<0, M>([&](auto l) {
+        constexpr int L = decltype(l)::value;
+        xr[L] = x[L];
+        xi[L] = x[M + L];
+        yr[L] = y[L];
+        yi[L] = y[M + L];
+    });
+    double rr[M], ii[M], ri[M], ir[M], zr[M], zi[M];
+    md_mul<M>(xr, yr, rr);
+    md_mul<M>(xi, yi, ii);
+    md_mul<M>(xr, yi, ri);
+    md_mul<M>(xi, yr, ir);
+    sfor<0, M>([&](auto l) { ii[decltype(l)::value] = -ii[decltype(l)::value]; });
+    md_add<M>(rr, ii, zr);
+    md_add<M>(ri, ir, zi);
+    sfor<0, M>([&](auto l) {
+        constexpr int L = decltype(l)::value;
+        z[L] = zr[L];
+        z[M + L] = zi[L];
+    });
+}
+
+template <int M>
+__device__ __forceinline__ void cmd_add(const double (&x)[2 * M], const double (&y)[2 * M], double (&z)[2 * M]) {
+    double xr[M], xi[M], yr[M], yi[M], zr[M], zi[M];
+    sfor<0, M>([&](auto l) {
+        constexpr int L = decltype(l)::value;
+        xr[L] = x[L];
+        xi[L] = x[M + L];
+        yr[L] = y[L];
+        yi[L] = y[M + L];
+    });
+    md_add<M>(xr, yr, zr);
+    md_add<M>(xi, yi, zi);
+    sfor<0, M>([&](auto l) {
+        constexpr int L = decltype(l)::value;
+        z[L] = zr[L];
+        z[M + L] = zi[L];
+    });
+}
+
+// One coefficient operation of the series' number field.
+template <int M, bool CX>
+__device__ __forceinline__ void coef_mul(const double (&x)[kCoef<M, CX>], const double (&y)[kCoef<M, CX>],
+                                         double (&z)[kCoef<M, CX>]) {
+    if constexpr (CX)
+        cmd_mul<M>(x, y, z);
+    else
+        md_mul<M>(x, y, z);
+}
+
+template <int M, bool CX>
+__device__ __forceinline__ void coef_add(const double (&x)[kCoef<M, CX>], const double (&y)[kCoef<M, CX>],
+                                         double (&z)[kCoef<M, CX>]) {
+    if constexpr (CX)
+        cmd_add<M>(x, y, z);
+    else
+        md_add<M>(x, y, z);
 }
 
 }  // namespace mdpe

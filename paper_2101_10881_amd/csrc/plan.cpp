@@ -28,13 +28,13 @@ namespace mdpe {
 
 static bool supported_m(int m) { return m == 1 || m == 2 || m == 3 || m == 4 || m == 5 || m == 8 || m == 10; }
 
-int choose_jobs_per_group(int d, int m) {
+int choose_jobs_per_group(int d, int w) {
     // Enough jobs per wavefront that the average lane load, J(d+1)(d+2)/2/64,
     // covers the longest output coefficient (d+1 multiply-adds); within the
     // LDS budget.
     int need = (2 * kLanes + (d + 2) - 1) / (d + 2);
     need = std::max(1, std::min(need, kLanes));
-    long per_job = (long)(d + 1) * m * 8;
+    long per_job = (long)(d + 1) * w * 8;
     long cap = std::max(1L, (long)kLdsBudget / per_job);
     return (int)std::max(1L, std::min((long)need, cap));
 }
@@ -115,7 +115,7 @@ static std::string check_hazards(const Plan &P) {
             int32_t w = jobs[q][2];
             // the second operand of a convolution is streamed while outputs are
             // written, so it may never be the job's own output
-            const bool conv_stage = stage <= P.n_layers() || stage > P.n_layers() + P.n_levels();
+            const bool conv_stage = stage <= P.n_layers() || stage > P.n_layers() + 1 + P.n_levels();
             if (conv_stage && jobs[q][1] == w) return "second operand is the output";
             if (w < 0 || w >= P.n_series) return "slot out of range";
             if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
@@ -136,16 +136,26 @@ static std::string check_hazards(const Plan &P) {
         auto e = stage_check(L, jobs);
         if (!e.empty()) return "conv layer " + std::to_string(L) + ": " + e;
     }
+    {
+        // the scale stage: job {src, dst, e} reads src and writes dst
+        std::vector<std::array<int32_t, 3>> jobs;
+        for (auto &c : P.scale) {
+            if (c[2] < 2 || c[2] > kMaxExponent) return "scale job with a bad exponent";
+            jobs.push_back({c[0], c[0], c[1]});
+        }
+        auto e = stage_check(P.n_layers() + 1, jobs);
+        if (!e.empty()) return "scale stage: " + e;
+    }
     for (int r = 1; r <= P.n_levels(); ++r) {
         std::vector<std::array<int32_t, 3>> jobs;
         for (int64_t q = P.add_off[r - 1]; q < P.add_off[r]; ++q) jobs.push_back({P.add[q][0], P.add[q][1], P.add[q][1]});
-        auto e = stage_check(P.n_layers() + r, jobs);
+        auto e = stage_check(P.n_layers() + 1 + r, jobs);
         if (!e.empty()) return "add level " + std::to_string(r) + ": " + e;
     }
     for (auto s : P.out_slots)
         if (s >= 0 && written[s] < 0) return "output slot never written";
     if (!P.corr.empty() || P.ybar_slot >= 0) {
-        const int stage = P.n_layers() + P.n_levels() + 1;
+        const int stage = P.n_layers() + P.n_levels() + 2;
         written[P.ybar_slot] = stage - 1;  // staged before the reverse layer
         auto e = stage_check(stage, P.corr);
         if (!e.empty()) return "reverse layer: " + e;
@@ -153,11 +163,16 @@ static std::string check_hazards(const Plan &P) {
     return "";
 }
 
-std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, uint32_t flags,
-                       Plan &P, bool *unsupported) {
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
+                       uint32_t flags, Plan &P, bool *unsupported) {
     *unsupported = false;
-    if (flags & ~kKeepMonomialValues) return "unknown flags";
+    if (flags & ~(kKeepMonomialValues | kComplex)) return "unknown flags";
     const bool keep = (flags & kKeepMonomialValues) != 0;
+    const bool cx = (flags & kComplex) != 0;
+    if (keep && cx) {
+        *unsupported = true;
+        return "the reverse pass (MDPE_KEEP_MONOMIAL_VALUES) is for real series only";
+    }
     if (n < 1 || N < 0 || d < 0) return "need n >= 1, N >= 0, d >= 0";
     if (!supported_m(m)) {
         *unsupported = true;
@@ -179,18 +194,49 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         nc += std::max(0, nk - 2);
         nmax = std::max(nmax, nk);
     }
+    // General exponents (Section 3): a table of powers z_i^p, p = 2..maxp[i],
+    // and one common-factor slot per monomial with an exponent above one.
+    std::vector<int> maxp(n, 0);
+    int64_t nfac = 0;
+    if (exps) {
+        int64_t q = 0;
+        for (int k = 0; k < N; ++k) {
+            bool any = false;
+            for (int j = 0; j < nvars[k]; ++j, ++q) {
+                const int e = exps[q];
+                if (e < 1 || e > kMaxExponent) return "monomial " + std::to_string(k) + ": exponent out of range 1..64";
+                maxp[vars[q]] = std::max(maxp[vars[q]], e - 1);
+                any |= e >= 2;
+            }
+            nfac += any;
+        }
+    }
+    int64_t npow = 0;
+    std::vector<int64_t> powoff(n, 0);  // slot of z_i^p is pbase + powoff[i] + p - 2
+    for (int i = 0; i < n; ++i) {
+        powoff[i] = npow;
+        npow += std::max(0, maxp[i] - 1);
+    }
+    if (keep && nfac > 0) {
+        *unsupported = true;
+        return "the reverse pass (MDPE_KEEP_MONOMIAL_VALUES) is for multilinear monomials only";
+    }
     const int64_t base = 1 + (int64_t)N + n;
     int64_t nmono2 = 0;  // monomials with n_k >= 2: they get an M_k slot when kept
     for (int k = 0; k < N; ++k) nmono2 += nvars[k] >= 2;
-    const int64_t mbase = base + tot + nb + nc;
+    const int64_t pbase = base + tot + nb + nc;  // powers, then common factors
+    const int64_t fbase = pbase + npow;
+    const int64_t mbase = fbase + nfac;
     const int64_t nser = mbase + (keep ? nmono2 + 1 + N + n : 0);
     if (nser > INT32_MAX / 2) {
         *unsupported = true;
         return "too many series for 32-bit slot indices";
     }
-    if ((long)(d + 1) * m * 8 > kMaxLdsBytes - 32768) {
+    const int w = cx ? 2 * m : m;
+    if ((long)(d + 1) * w * 8 > kMaxLdsBytes - 32768) {
         *unsupported = true;
-        return "d too large: one convolution operand must fit in one workgroup's LDS ((d+1)m*8 <= 131072 bytes)";
+        return "d too large: one convolution operand must fit in one workgroup's LDS ((d+1)w*8 <= 131072 bytes, "
+               "w = m doubles per coefficient, 2m for complex series)";
     }
     if (d + 1 > 65535) {
         *unsupported = true;
@@ -201,28 +247,61 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     P.N = N;
     P.d = d;
     P.m = m;
+    P.w = w;
     P.flags = flags;
     P.n_series = nser;
 
     std::vector<std::vector<std::array<int32_t, 3>>> layers(std::max(nmax, 1));
+    auto add_job = [&](int layer, int32_t t1, int32_t t2, int32_t t3) {
+        if ((int)layers.size() < layer) layers.resize(layer);
+        layers[layer - 1].push_back({t1, t2, t3});
+    };
     std::vector<int32_t> value_list{0};
     std::vector<std::vector<int32_t>> grad_lists(n);
     std::vector<int32_t> mono_slot(N, -1);  // slot holding M_k = prod of the monomial's variables
     for (int s = 0; s < 1 + N + n; ++s) P.stage.push_back({s, s});
 
-    int64_t alpha = 0, beta = 0, gamma = 0, pos = 0, mpos = 0;
+    // table of powers: z_i^p := z_i^{p-1} * z_i at layer p-1, ready after it
+    auto pow_slot = [&](int i, int p) {
+        return p == 1 ? (int32_t)(1 + N + i) : (int32_t)(pbase + powoff[i] + p - 2);
+    };
+    for (int i = 0; i < n; ++i)
+        for (int p = 2; p <= maxp[i]; ++p) add_job(p - 1, pow_slot(i, p - 1), (int32_t)(1 + N + i), pow_slot(i, p));
+
+    int64_t alpha = 0, beta = 0, gamma = 0, pos = 0, mpos = 0, fpos = 0;
     for (int k = 0; k < N; ++k) {
         const int nk = nvars[k];
         const int32_t *v = vars + pos;
-        auto A = [&](void) { return (int32_t)(k + 1); };
+        const int32_t *e = exps ? exps + pos : nullptr;
+        // common factor a_k * prod_j z_{i_j}^{e_j - 1}, in increasing j; the
+        // monomial's own jobs follow it, `shift` layers later
+        int32_t a_slot = (int32_t)(k + 1);
+        int shift = 0;
+        for (int j = 0; e && j < nk; ++j) {
+            if (e[j] < 2) continue;
+            const int32_t fac = (int32_t)(fbase + fpos);
+            const int ready = e[j] - 1 >= 2 ? e[j] - 2 : 0;
+            shift = std::max(shift, ready) + 1;
+            add_job(shift, a_slot, pow_slot(v[j], e[j] - 1), fac);
+            a_slot = fac;
+        }
+        if (a_slot != (int32_t)(k + 1)) ++fpos;
+        auto A = [&](void) { return a_slot; };
         auto Z = [&](int i) { return (int32_t)(1 + N + v[i - 1]); };  // z_{i_i}, 1-based position
         auto F = [&](int j) { return (int32_t)(base + alpha + j - 1); };
         auto B = [&](int j) { return (int32_t)(base + tot + beta + j - 1); };
         auto C = [&](int j) { return (int32_t)(base + tot + nb + gamma + j - 1); };
-        auto job = [&](int layer, int32_t t1, int32_t t2, int32_t t3) { layers[layer - 1].push_back({t1, t2, t3}); };
+        auto job = [&](int layer, int32_t t1, int32_t t2, int32_t t3) { add_job(layer + shift, t1, t2, t3); };
+        // a z^e factor's partial derivative is e times the multilinear one
+        auto scale = [&](int j0, int32_t src, int32_t dst) {
+            if (e && e[j0] >= 2) P.scale.push_back({src, dst, e[j0]});
+        };
         if (nk == 1) {
             job(1, A(), Z(1), F(1));
-            P.stage.push_back({B(1), (int32_t)(k + 1)});
+            if (e && e[0] >= 2)
+                scale(0, A(), B(1));
+            else
+                P.stage.push_back({B(1), (int32_t)(k + 1)});
             value_list.push_back(F(1));
             grad_lists[v[0]].push_back(B(1));
             mono_slot[k] = Z(1);
@@ -233,6 +312,8 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
                 job(1, Z(2), A(), B(1));
                 grad_lists[v[0]].push_back(B(1));
                 grad_lists[v[1]].push_back(F(1));
+                scale(0, B(1), B(1));
+                scale(1, F(1), F(1));
                 if (keep) {
                     mono_slot[k] = (int32_t)(mbase + mpos++);
                     job(1, Z(2), Z(1), mono_slot[k]);  // M_k = z_{i_2} * z_{i_1}
@@ -254,6 +335,9 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
                 grad_lists[v[0]].push_back(B(nk - 2));
                 for (int j = 1; j <= nk - 2; ++j) grad_lists[v[j]].push_back(C(j));
                 grad_lists[v[nk - 1]].push_back(F(nk - 1));
+                scale(0, B(nk - 2), B(nk - 2));
+                for (int j = 1; j <= nk - 2; ++j) scale(j, C(j), C(j));
+                scale(nk - 1, F(nk - 1), F(nk - 1));
             }
             value_list.push_back(F(nk));
         }
@@ -300,7 +384,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     auto err = check_hazards(P);
     if (!err.empty()) return "internal planner error: " + err;
 
-    P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, m));
+    P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, w));
     return "";
 }
 

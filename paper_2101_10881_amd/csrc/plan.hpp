@@ -13,6 +13,7 @@ namespace mdpe {
 constexpr int kLanes = 64;             // one wavefront per convolution workgroup
 constexpr int kMaxLdsBytes = 163840;   // LDS one gfx950 workgroup may allocate
 constexpr int kLdsBudget = 65536;      // LDS a workgroup aims to stay under (>= 2 per CU)
+constexpr int kMaxExponent = 64;
 
 struct LaneSchedule {
     int jobs_per_group = 1;            // J: convolution jobs staged per workgroup
@@ -24,9 +25,11 @@ struct LaneSchedule {
 };
 
 constexpr uint32_t kKeepMonomialValues = 1u;
+constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then imaginary limbs
 
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
+    int w = 0;                         // doubles per coefficient: m, or 2m for complex series
     uint32_t flags = 0;
     int64_t n_series = 0;
     // convolution jobs {t1, t2, t3} in launch order; layer L spans
@@ -39,6 +42,9 @@ struct Plan {
     std::vector<int32_t> out_slots;    // [1+n]: value slot, then d/dz_i slot or -1
     // staging copies {slot, source}: source s < N+1 is coeff series s, else z series s-N-1
     std::vector<std::array<int32_t, 2>> stage;
+    // general exponents: scale jobs {src, dst, e}, A[dst] := e * A[src] per
+    // coefficient, run after the last convolution layer, before the additions
+    std::vector<std::array<int32_t, 3>> scale;
     LaneSchedule lanes;
     // reverse pass (flags & kKeepMonomialValues): one layer of correlation jobs
     // {t1 = ybar slot, t2 = M_k or gradient slot, t3 = output slot}
@@ -47,16 +53,18 @@ struct Plan {
     std::vector<int32_t> coeff_bar_slots;   // [N+1]: ybar slot, then abar_k slots
     std::vector<int32_t> z_bar_slots;       // [n]: zbar_i slot or -1 (absent variable)
 
+    bool complex_series() const { return (flags & kComplex) != 0; }
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };
 
 // Returns "" on success, else a message; *unsupported distinguishes limits
 // of this implementation from invalid input.
-std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, uint32_t flags,
-                       Plan &out, bool *unsupported);
+// exps: NULL (every exponent one) or [sum nvars] exponents in 1..kMaxExponent.
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
+                       uint32_t flags, Plan &out, bool *unsupported);
 
 LaneSchedule make_lane_schedule(int d, int jobs_per_group);
-int choose_jobs_per_group(int d, int m);
+int choose_jobs_per_group(int d, int w);
 
 }  // namespace mdpe

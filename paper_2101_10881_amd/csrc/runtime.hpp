@@ -21,6 +21,7 @@ struct mdpe_plan {
     int *d_cbar = nullptr;
     int *d_zbar = nullptr;
     int *d_ybar = nullptr;
+    int4 *d_scale = nullptr;
 };
 
 namespace mdpe {

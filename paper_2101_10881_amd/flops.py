@@ -16,6 +16,8 @@ with; "instructions" counts each FP64 VALU operation once.
 
 Per convolution job (eq. (1) of the paper, computed without the zero terms):
 (d+1)(d+2)/2 md_mul and d(d+1)/2 md_add.  Per addition job: d+1 md_add.
+Complex series (cx=True): a complex multiplication is four md_mul and two
+md_add, a complex addition two md_add.
 The paper's own convention (Section 6.2) charges the zero-inserted square,
 (d+1)^2 md_mul and d(d+1) md_add, at 3089 and 397 double operations per
 deca-double multiplication and addition; ``paper_convention`` reproduces it.
@@ -57,22 +59,31 @@ def conv_md_ops(d: int):
     return (d + 1) * (d + 2) // 2, d * (d + 1) // 2
 
 
-def conv_flops(m: int, d: int) -> int:
+def coef_flops(op: str, m: int, cx: bool = False) -> int:
+    """FLOPs of one coefficient multiplication or addition (real or complex)."""
+    if not cx:
+        return md_flops(op, m)
+    if op == "mul":
+        return 4 * md_flops("mul", m) + 2 * md_flops("add", m)
+    return 2 * md_flops("add", m)
+
+
+def conv_flops(m: int, d: int, cx: bool = False) -> int:
     nm, na = conv_md_ops(d)
-    return nm * md_flops("mul", m) + na * md_flops("add", m)
+    return nm * coef_flops("mul", m, cx) + na * coef_flops("add", m, cx)
 
 
-def add_flops(m: int, d: int) -> int:
-    return (d + 1) * md_flops("add", m)
+def add_flops(m: int, d: int, cx: bool = False) -> int:
+    return (d + 1) * coef_flops("add", m, cx)
 
 
-def conv_bytes(m: int, d: int) -> int:
+def conv_bytes(m: int, d: int, cx: bool = False) -> int:
     """Algorithmic HBM bytes of one convolution job: read two series, write one."""
-    return 3 * (d + 1) * m * 8
+    return 3 * (d + 1) * m * 8 * (2 if cx else 1)
 
 
-def add_bytes(m: int, d: int) -> int:
-    return 3 * (d + 1) * m * 8
+def add_bytes(m: int, d: int, cx: bool = False) -> int:
+    return 3 * (d + 1) * m * 8 * (2 if cx else 1)
 
 
 PAPER_DECA_COST = {"mul": 3089, "add": 397}

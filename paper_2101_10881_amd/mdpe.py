@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdpe.h")
 
 MDPE_OK, MDPE_EINVAL, MDPE_EUNSUPPORTED, MDPE_ENOMEM, MDPE_EDEVICE = 0, -1, -2, -3, -4
 MDPE_KEEP_MONOMIAL_VALUES = 1
+MDPE_COMPLEX = 2
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -33,7 +34,7 @@ class MdpeError(RuntimeError):
 class PolyDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("nvars", ctypes.POINTER(ctypes.c_int32)), ("vars", ctypes.POINTER(ctypes.c_int32)),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("exps", ctypes.POINTER(ctypes.c_int32))]
 
 
 class PlanInfo(ctypes.Structure):
@@ -41,7 +42,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_layers", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("jobs_per_group", ctypes.c_int32), ("lane_steps", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +91,7 @@ def lib():
     L.plan_conv_jobs.argtypes = [_vp, _i32p]
     L.plan_add_jobs.argtypes = [_vp, _i32p]
     L.plan_outputs.argtypes = [_vp, _i32p]
+    L.plan_scale_jobs.argtypes = [_vp, _i32p]
     L.eval_and_diff.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.eval_and_diff_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.profiler_create.argtypes = [ctypes.POINTER(_vp)]
@@ -153,11 +155,15 @@ def _stream(stream):
 class Plan:
     """A plan (plan_polynomial); device -1 builds a host-only plan for inspection."""
 
-    def __init__(self, n, nvars, vars_, d, m, device=0, flags=0):
+    def __init__(self, n, nvars, vars_, d, m, device=0, flags=0, exps=None):
         self.nvars = np.ascontiguousarray(nvars, dtype=np.int32)
         self.vars = np.ascontiguousarray(vars_, dtype=np.int32)
+        self.exps = None if exps is None else np.ascontiguousarray(exps, dtype=np.int32)
+        if self.exps is not None and self.exps.shape != self.vars.shape:
+            raise ValueError("exps must have one exponent per entry of vars")
         desc = PolyDesc(int(n), int(self.nvars.shape[0]), int(d), int(m),
-                        self.nvars.ctypes.data_as(_i32p), self.vars.ctypes.data_as(_i32p), int(flags))
+                        self.nvars.ctypes.data_as(_i32p), self.vars.ctypes.data_as(_i32p), int(flags),
+                        self.exps.ctypes.data_as(_i32p) if self.exps is not None else None)
         h = _vp()
         _check(lib().plan_polynomial(ctypes.byref(desc), int(device), ctypes.byref(h)))
         self._h = h
@@ -168,7 +174,9 @@ class Plan:
 
     @classmethod
     def for_workload(cls, w, device=0, flags=0):
-        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, flags)
+        if getattr(w, "cx", False):
+            flags |= MDPE_COMPLEX
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, flags, getattr(w, "exps", None))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -205,6 +213,11 @@ class Plan:
         out = np.zeros(1 + self.info["n"], dtype=np.int32)
         _check(lib().plan_outputs(self._h, out.ctypes.data_as(_i32p)))
         return out
+
+    def scale_jobs(self):
+        rows = np.zeros((max(self.info["n_scale"], 1), 3), dtype=np.int32)
+        _check(lib().plan_scale_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[: self.info["n_scale"]]
 
 
 def plan_polynomial(n, nvars, vars_, d, m, device=0) -> Plan:
@@ -251,10 +264,16 @@ def eval_adjoint(plan: Plan, ybar, workspace, coeff_bar, z_bar, stream=None, pro
 
 
 def md_elementwise(op, x, y, z, stream=None):
-    """z = x op y on planar [m][count] float64 device tensors; op 'add' or 'mul'."""
-    m, count = x.shape
-    _check(lib().md_elementwise({"add": 0, "mul": 1}[op], int(m), int(count), _ptr(x), _ptr(y), _ptr(z),
-                                _stream(stream)))
+    """z = x op y on float64 device tensors: op 'add' or 'mul' on planar [m][count],
+    'cadd' or 'cmul' on complex [2][m][count] (real limbs, then imaginary limbs)."""
+    code = {"add": 0, "mul": 1, "cadd": 2, "cmul": 3}[op]
+    if x.dim() != (3 if code >= 2 else 2) or x.shape[0] != (2 if code >= 2 else x.shape[0]):
+        raise ValueError(f"{op}: bad operand shape {tuple(x.shape)}")
+    m, count = x.shape[-2], x.shape[-1]
+    for t in (x, y, z):
+        if t.shape != x.shape or not t.is_contiguous():
+            raise ValueError("x, y, z must be contiguous tensors of one shape")
+    _check(lib().md_elementwise(code, int(m), int(count), _ptr(x), _ptr(y), _ptr(z), _stream(stream)))
 
 
 class Polynomial:
@@ -262,23 +281,30 @@ class Polynomial:
 
     >>> P = Polynomial(n, nvars, vars, d, m)
     >>> value, grad = P.eval_and_diff(coeff, z)   # float64 tensors [m][N+1][d+1], [m][n][d+1]
+
+    complex=True: complex series, every tensor with a leading axis of two
+    (real parts, then imaginary parts), e.g. coeff [2][m][N+1][d+1].
+    exps: one exponent per entry of vars_ (None: every exponent one).
     """
 
-    def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False):
+    def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
-        flags = MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0
-        self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags)
+        flags = (MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0) | (MDPE_COMPLEX if complex else 0)
+        self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
+        self.complex = bool(complex)
+        self._lead = (2, self.m) if complex else (self.m,)
         nbytes = int(self.plan.info["workspace_bytes"])
         # 256-byte aligned by the caching allocator
         self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
 
     @classmethod
     def for_workload(cls, w, device=None, keep_monomials=False):
-        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials)
+        return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
+                   getattr(w, "exps", None))
 
     def new_workspace(self):
         import torch
@@ -297,8 +323,8 @@ class Polynomial:
 
     def _check_inputs(self, coeff, z):
         import torch
-        for name, t, shape in (("coeff", coeff, (self.m, self.N + 1, self.d + 1)),
-                               ("z", z, (self.m, self.n, self.d + 1))):
+        for name, t, shape in (("coeff", coeff, self._lead + (self.N + 1, self.d + 1)),
+                               ("z", z, self._lead + (self.n, self.d + 1))):
             if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
                 raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
 
@@ -307,9 +333,13 @@ class Polynomial:
         self._check_inputs(coeff, z)
         ws = self.workspace if workspace is None else workspace
         if value is None:
-            value = torch.empty((self.m, self.d + 1), dtype=torch.float64, device=self.device)
+            value = torch.empty(self._lead + (self.d + 1,), dtype=torch.float64, device=self.device)
         if grad is None:
-            grad = torch.empty((self.m, self.n, self.d + 1), dtype=torch.float64, device=self.device)
+            grad = torch.empty(self._lead + (self.n, self.d + 1), dtype=torch.float64, device=self.device)
+        for name, t, shape in (("value", value, self._lead + (self.d + 1,)),
+                               ("grad", grad, self._lead + (self.n, self.d + 1))):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
+                raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
         if profiler is None:
             eval_and_diff(self.plan, coeff, z, value, grad, ws, stream)
         else:

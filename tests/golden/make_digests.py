@@ -25,14 +25,14 @@ def digest(a) -> str:
 def main():
     out = {"_source": "oracle/oracle.c via tests/golden/make_digests.py; inputs from paper_2101_10881_amd.workloads",
            "workloads": {}}
-    for name, w in (("config1", W.config1()),):
+    for name, w in (("config1", W.config1()), ("config1_complex", W.config1(cx=True))):
         t = time.time()
         val, grad = O.eval_workload(w, nthreads=os.cpu_count())
         out["workloads"][name] = {
             "name": w.name, "m": w.m, "d": w.d, "n": w.n, "N": w.N, "seed": 1,
             "value_sha256": digest(val), "grad_sha256": digest(grad),
-            "value_head": [float(v).hex() for v in val[:, 0]],
-            "grad_head": [float(v).hex() for v in grad[:, 0, 0]],
+            "value_head": [float(v).hex() for v in val[..., 0].ravel()],
+            "grad_head": [float(v).hex() for v in grad[..., 0, 0].ravel()],
         }
         print(name, "%.1fs" % (time.time() - t), flush=True)
     with open(os.path.join(HERE, "digests.json"), "w") as f:

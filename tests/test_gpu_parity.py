@@ -5,7 +5,8 @@ per-job operation order, so every limb must agree exactly (integer
 comparison of the binary64 bit patterns, signed zeros included).  Cases
 span several workgroup tiles and ragged tails: all seven precisions,
 degrees 0..255, monomials with 1..12 variables, absent variables, N = 0,
-and the benchmark workloads at full size (c1 against a digest of the
+the three test polynomial shapes at sweep points, and the benchmark
+workloads at full size (c1 against a digest of the
 oracle's output written by tests/golden/make_digests.py).
 """
 import json
@@ -112,6 +113,19 @@ def test_config2_bitexact(oracle_lib):
 
 def test_config4_forward_bitexact(oracle_lib):
     _compare(oracle_lib, W.config4())
+
+
+def test_p3_shape_bitexact(oracle_lib):
+    # all 8128 two-variable monomials of 128 variables (addition-heavy)
+    _compare(oracle_lib, W.p3(m=3, d=8))
+
+
+@pytest.mark.parametrize("poly,m,d", [("p1", 1, 191), ("p1", 5, 95), ("p2", 2, 31), ("p3", 8, 15)])
+def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
+    # points of the precision x degree sweep: other lane schedules (two jobs
+    # per workgroup at d = 95) and precisions than the benchmark configuration
+    build = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly]
+    _compare(oracle_lib, build(m=m, d=d))
 
 
 def test_config1_full_size_digest():

@@ -124,6 +124,8 @@ def _execute_exact(p, w):
             A[base] = a[k + 1]
     for layer, t1, t2, t3 in p.conv_jobs():
         A[t3] = E.smul(A[t1], A[t2])
+    for src, dst, e in p.scale_jobs():
+        A[dst] = [c * int(e) for c in A[src]]
     for level, t1, t2 in p.add_jobs():
         A[t2] = E.sadd(A[t2], A[t1])
     out = p.outputs()
@@ -230,3 +232,74 @@ def test_keep_monomials_plan_computes_the_adjoint(seed):
     for i in range(n):
         if any(i in s_ for s_ in sup):
             assert any(A[t3] == corr(ybar, eg[i]) for (t2, t3) in outs), f"zbar_{i}"
+
+
+def test_complex_plan_same_jobs_double_workspace():
+    w = W.random_poly("cx", 3, 9, 7, 11, [1, 2, 3, 4, 5, 3, 2, 6, 7, 2, 3], seed=4)
+    p = mdpe.Plan.for_workload(w, device=-1)
+    pc = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_COMPLEX)
+    assert pc.info["flags"] == mdpe.MDPE_COMPLEX
+    assert pc.info["workspace_bytes"] == 2 * p.info["workspace_bytes"]
+    assert np.array_equal(pc.conv_jobs(), p.conv_jobs())
+    assert np.array_equal(pc.add_jobs(), p.add_jobs())
+    assert np.array_equal(pc.outputs(), p.outputs())
+
+
+@pytest.mark.parametrize("flags, m, d, code", [
+    (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
+    (mdpe.MDPE_COMPLEX, 10, 819, mdpe.MDPE_EUNSUPPORTED),   # (d+1)*2m*8 > 131072
+    (4, 2, 3, mdpe.MDPE_EINVAL),                             # unknown flag
+])
+def test_complex_plan_limits(flags, m, d, code):
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Plan(4, [2], [0, 1], d, m, device=-1, flags=flags)
+    assert e.value.code == code
+    mdpe.Plan(4, [2], [0, 1], 818, 10, device=-1, flags=mdpe.MDPE_COMPLEX)      # the largest complex d at m = 10
+    mdpe.Plan(4, [2], [0, 1], 819, 10, device=-1)                               # still fine when real
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plan_jobs_with_exponents_compute_the_definition(seed):
+    """Power table, common factors and exponent scale jobs, run in exact
+    arithmetic, give the value and gradient of sum_k a_k prod z^e."""
+    rng = np.random.default_rng(140 + seed)
+    n = int(rng.integers(1, 7))
+    N = int(rng.integers(1, 7))
+    w = W.with_exponents(W.random_poly("plan_e", 1, 3, n, N, rng.integers(1, n + 1, size=N), seed), 5, seed=seed)
+    p = mdpe.Plan.for_workload(w, device=-1)
+    assert p.info["n_scale"] == int(np.sum(w.exps >= 2))
+    val, grad = _execute_exact(p, w)
+    (ev, eg), _ = E.workload_exact(w)
+    assert val == ev
+    assert grad == eg
+
+
+def test_unit_exponents_give_the_multilinear_plan():
+    w = W.random_poly("ones", 2, 4, 6, 9, [1, 2, 3, 4, 5, 3, 2, 6, 3], seed=5)
+    p0 = mdpe.Plan.for_workload(w, device=-1)
+    w.exps = np.ones_like(w.vars)
+    p1 = mdpe.Plan.for_workload(w, device=-1)
+    assert p1.info == p0.info
+    assert np.array_equal(p1.conv_jobs(), p0.conv_jobs()) and np.array_equal(p1.add_jobs(), p0.add_jobs())
+
+
+def test_exponent_layers():
+    # x0^3 x1 * a: the power z0^2 at layer 1, the common factor a z0^2 at layer 2,
+    # then the monomial's two layers
+    w = W.make("layers", 1, 2, 2, [(0, 1)], seed=1)
+    w.exps = np.array([3, 1], dtype=np.int32)
+    p = mdpe.Plan.for_workload(w, device=-1)
+    assert p.layer_sizes()[0] == [1, 1, 2, 1]
+    assert [tuple(r) for r in p.scale_jobs()] == [(p.outputs()[1], p.outputs()[1], 3)]
+
+
+@pytest.mark.parametrize("exps, flags, code", [
+    ([1, 0], 0, mdpe.MDPE_EINVAL),
+    ([65, 1], 0, mdpe.MDPE_EINVAL),
+    ([2, 1], mdpe.MDPE_KEEP_MONOMIAL_VALUES, mdpe.MDPE_EUNSUPPORTED),
+])
+def test_exponent_limits(exps, flags, code):
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Plan(4, [2], [0, 1], 3, 2, device=-1, flags=flags, exps=exps)
+    assert e.value.code == code
+    mdpe.Plan(4, [2], [0, 1], 3, 2, device=-1, flags=mdpe.MDPE_KEEP_MONOMIAL_VALUES, exps=[1, 1])
