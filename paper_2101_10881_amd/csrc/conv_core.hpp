@@ -64,6 +64,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
         if (lane == 0) jd[j] = t;
     }
     __syncthreads();
+    if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barrier)
 
     const int *my = chains + (long)lane * stride;
     // Next position in the lane's chain list (reads the -1 terminator at most).
@@ -150,13 +151,21 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     }
 }
 
-template <int M, bool CORR, bool CX = false>
-__global__ __launch_bounds__(64) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
-                                                        int njobs, int d, int J, const int *__restrict__ chains,
-                                                        int stride, int steps) {
+// WPB wavefronts per workgroup (1 or 4), each with its own group of J jobs and
+// its own LDS region of group_bytes.  Four-wavefront workgroups put one
+// wavefront on each SIMD of a CU; the launcher uses them when a layer has
+// between one and three wavefronts per SIMD, where single-wavefront workgroups
+// can pile three onto one SIMD while another stays idle.  (A separate
+// instantiation: the 256-thread launch bound alone slows a lone wavefront.)
+template <int M, bool CORR, bool CX = false, int WPB = 1>
+__global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                              int njobs, int d, int J, const int *__restrict__ chains,
+                                                              int stride, int steps, int group_bytes) {
     extern __shared__ double lds[];
-    const int g0 = blockIdx.x * J;
-    conv_group<M, CORR, CX>(A, jobs + g0, min(J, njobs - g0), J, d, lds, chains, stride, steps, threadIdx.x);
+    const int wave = WPB == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int g0 = (blockIdx.x * WPB + wave) * J;
+    conv_group<M, CORR, CX>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
+                            chains, stride, steps, threadIdx.x & 63);
 }
 
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).

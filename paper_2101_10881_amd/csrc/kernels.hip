@@ -249,23 +249,45 @@ int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
         if (e_ != hipSuccess) return fail(MDPE_EDEVICE, std::string(what ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+int simd_count(int device) {
+    static int cached[64] = {0};
+    if (device < 0 || device >= 64) return 1024;
+    if (!cached[device]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[device] = 4 * cus;
+    }
+    return cached[device];
+}
+
 template <int M, bool CORR, bool CX>
 int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
-    const size_t lds = conv_lds_bytes(P.d, mdpe::kCoef<M, CX>, J, P.lanes.stride);
+    const size_t group_bytes = (conv_lds_bytes(P.d, mdpe::kCoef<M, CX>, J, P.lanes.stride) + 15) / 16 * 16;
     static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX>,
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set = true;
     }
     if (nj == 0) return MDPE_OK;
     const int groups = (nj + J - 1) / J;
+    // one wavefront per workgroup, or one per SIMD (see conv_layer_kernel)
+    const int simds = simd_count(pl->device);
+    const int wpb = (groups > simds && groups <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
+    const int blocks = (groups + wpb - 1) / wpb;
     int rc = record(prof, 1, st, true);
     if (rc) return rc;
-    hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX>), dim3(groups), dim3(64), lds, st, A, jobs, nj, P.d, J,
-                       pl->d_chains, P.lanes.stride, P.lanes.steps);
+    if (wpb == 4)
+        hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4>), dim3(blocks), dim3(256), 4 * group_bytes, st, A,
+                           jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps, (int)group_bytes);
+    else
+        hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1>), dim3(blocks), dim3(64), group_bytes, st, A,
+                           jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps, (int)group_bytes);
     LAUNCH_CHECK("conv_layer_kernel");
     return record(prof, 1, st, false);
 }
