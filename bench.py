@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--ms", default="1,2,3,4,5,8,10", help="sweep: precisions")
     ap.add_argument("--ds", default="0,8,15,31,63,95,127,152,159,191", help="sweep: degrees")
     ap.add_argument("--complex", action="store_true", help="sweep: complex series")
+    ap.add_argument("--emax", type=int, default=1,
+                    help="sweep: raise half of the variable occurrences to exponents 2..emax")
     ap.add_argument("--instances", type=int, default=512, help="c3: number of instances")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-vs-plain (c3) and autograd (c4) side measurements")
@@ -244,9 +246,10 @@ def measure_complex(steps, warmup, m=10, d=152):
             "conv_TFLOPs": round(conv_f / (cnv * 1e-3) / 1e12, 3)}
 
 
-def sweep_workload(poly, m, d, cx=False):
+def sweep_workload(poly, m, d, cx=False, emax=1):
     from paper_2101_10881_amd import workloads as W
-    return {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
+    w = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
+    return W.with_exponents(w, emax, seed=1) if emax > 1 else w
 
 
 def run_sweep(a):
@@ -262,7 +265,7 @@ def run_sweep(a):
     for poly in a.polys.split(","):
         for m in (int(x) for x in a.ms.split(",")):
             for d in (int(x) for x in a.ds.split(",")):
-                w = sweep_workload(poly, m, d, a.complex)
+                w = sweep_workload(poly, m, d, a.complex, a.emax)
                 P = mdpe.Polynomial.for_workload(w, dev)
                 coeff = torch.from_numpy(w.coeff).to(dev)
                 z = torch.from_numpy(w.z).to(dev)
@@ -278,8 +281,9 @@ def run_sweep(a):
                 t = prof.read()
                 info = P.plan.info
                 work = (info["n_conv"] * flops.conv_flops(m, d, a.complex)
-                        + info["n_add"] * flops.add_flops(m, d, a.complex))
-                row = {"poly": poly, "complex": a.complex, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
+                        + info["n_add"] * flops.add_flops(m, d, a.complex)
+                        + info["n_scale"] * (d + 1) * flops.md_flops("mul", m) * (2 if a.complex else 1))
+                row = {"poly": poly, "complex": a.complex, "emax": a.emax, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
                        "add_ms": round(t["add_ms"] / reps, 4), "sum_ms": round((t["cnv_ms"] + t["add_ms"]) / reps, 4),
                        "wall_ms": round(wall, 4), "n_conv": info["n_conv"], "n_add": info["n_add"],
                        "TFLOPs": round(work / (t["cnv_ms"] + t["add_ms"]) * reps / 1e9, 3)}

@@ -346,7 +346,10 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         const mdpe::LaneSchedule &S = scheds[sched_index[key]];
         const int G = t.groups_per_task > 0 ? t.groups_per_task : std::max(1, (256 + S.steps - 1) / S.steps);
         const long items_per_task = t.add_items_per_task > 0 ? t.add_items_per_task : 4096;
-        lds = std::max(lds, (size_t)mdpe::conv_lds_jobs_offset((long)J * (P.d + 1) * P.m) + (size_t)J * 16);
+        lds = std::max(lds, (size_t)mdpe::conv_lds_jobs_offset((long)J * (P.d + 1) * mdpe::lds_doubles_per_coef(P.m)) +
+                                (size_t)J * 16);
+        if (lds > (size_t)mdpe::kMaxLdsBytes)
+            return bfail(MDPE_EUNSUPPORTED, "a tile's jobs_per_group needs more LDS than one workgroup has");
         mdpe::BatchInst &I = B->insts[p];
         std::memset(&I, 0, sizeof(I));
         I.conv = plans[p]->d_conv;

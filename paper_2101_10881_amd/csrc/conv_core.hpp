@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "md.hpp"
+#include "plan.hpp"
 
 namespace mdpe {
 
@@ -30,8 +31,9 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
     st.i = 0;
 }
 
-// LDS layout of one workgroup: X[J][d+1][W] doubles (the first operands),
-// then the J job descriptors (16-byte aligned).
+// LDS layout of one wavefront's group: X[J][d+1][W] doubles (the first
+// operands), Y[J][d+1][W] (the second operands, only when
+// stages_second_operand(W)), then the J job descriptors (16-byte aligned).
 __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
 
 // CORR = false: convolution z_k = sum_{i=0..k} x_i y_{k-i} (eq. (1)).
@@ -41,26 +43,33 @@ __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xd
 // CX = true: complex series, W = 2M doubles per coefficient (cmd_mul, cmd_add).
 // One 64-lane wavefront computes jn <= J jobs jobs[0..jn) (the output
 // coefficients of each spread over the lanes by the schedule `chains`).
-// lds must hold conv_lds_jobs_offset(J*(d+1)*W) + J*16 bytes.  Ends with the
-// wavefront's stores issued (not necessarily complete).
+// lds must hold conv_lds_jobs_offset(J*(d+1)*lds_doubles_per_coef(W)) + J*16
+// bytes.  Ends with the wavefront's stores issued (not necessarily complete).
 template <int M, bool CORR, bool CX = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
                                            int steps, int lane) {
     constexpr int W = kCoef<M, CX>;
+    constexpr bool YL = stages_second_operand(W);
     const long S = (long)(d + 1) * W;
     double *X = lds;
-    int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * S));
+    double *Y = lds + J * S;  // used when YL
+    int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * (YL ? 2 : 1) * S));
     // Stage the first operand of every job in LDS: it is read by all lanes and
     // may be the job's own output (the in-place b := b * a of Section 3).  The
     // second operand is never the output (the planner checks) and is streamed
     // from global memory -- mostly one of the shared input series, so it stays
-    // in L2.  The first operand is read from LDS one step ahead of its use,
-    // the second from global memory two steps ahead.
+    // in L2 -- except for coefficients of at most two doubles, where a step is
+    // so short that its latency would dominate: then it is staged too.  The
+    // first operand is read one step ahead of its use, the second two steps.
     for (int j = 0; j < jn; ++j) {
         const int4 t = jobs[j];
         const double *xs = A + (long)t.x * S;
         for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+        if (YL) {
+            const double *ys = A + (long)t.y * S;
+            for (long q = lane; q < S; q += 64) Y[j * S + q] = ys[q];
+        }
         if (lane == 0) jd[j] = t;
     }
     __syncthreads();
@@ -93,7 +102,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     double p[W];
     {
         const double *xp = X + st.j * S + xidx(st.k, 0) * W;
-        const double *yp = A + (long)job.y * S + (long)yidx(st.k, 0) * W;
+        const double *yp = YL ? Y + st.j * S + yidx(st.k, 0) * W : A + (long)job.y * S + (long)yidx(st.k, 0) * W;
         double x0[W], y0[W];
 #pragma unroll
         for (int l = 0; l < W; ++l) {
@@ -107,7 +116,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     advance(st, nx, njob);
     double yn[W];
     {
-        const double *yp = A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * W;
+        const double *yp = YL ? Y + nx.j * S + yidx(nx.k, nx.i) * W : A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * W;
         const bool fetch = nx.live && 1 < steps;
 #pragma unroll
         for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
@@ -127,7 +136,8 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 #pragma unroll
             for (int l = 0; l < W; ++l) x1[l] = xp[l];
             const bool fetch = n2.live && s + 2 < steps;
-            const double *yp = A + (long)n2job.y * S + (long)yidx(n2.k, n2.i) * W;
+            const double *yp = YL ? Y + n2.j * S + yidx(n2.k, n2.i) * W
+                                  : A + (long)n2job.y * S + (long)yidx(n2.k, n2.i) * W;
 #pragma unroll
             for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
         }

@@ -265,7 +265,8 @@ template <int M, bool CORR, bool CX>
 int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
-    const size_t group_bytes = (conv_lds_bytes(P.d, mdpe::kCoef<M, CX>, J, P.lanes.stride) + 15) / 16 * 16;
+    const size_t group_bytes =
+        (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J, P.lanes.stride) + 15) / 16 * 16;
     static bool attr_set = false;
     if (!attr_set) {
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1>,

@@ -34,7 +34,7 @@ int choose_jobs_per_group(int d, int w) {
     // LDS budget.
     int need = (2 * kLanes + (d + 2) - 1) / (d + 2);
     need = std::max(1, std::min(need, kLanes));
-    long per_job = (long)(d + 1) * w * 8;
+    long per_job = (long)(d + 1) * lds_doubles_per_coef(w) * 8;
     long cap = std::max(1L, (long)kLdsBudget / per_job);
     return (int)std::max(1L, std::min((long)need, cap));
 }
@@ -233,10 +233,11 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         return "too many series for 32-bit slot indices";
     }
     const int w = cx ? 2 * m : m;
-    if ((long)(d + 1) * w * 8 > kMaxLdsBytes - 32768) {
+    if ((long)(d + 1) * lds_doubles_per_coef(w) * 8 > kMaxLdsBytes - 32768) {
         *unsupported = true;
-        return "d too large: one convolution operand must fit in one workgroup's LDS ((d+1)w*8 <= 131072 bytes, "
-               "w = m doubles per coefficient, 2m for complex series)";
+        return "d too large: a convolution job's LDS operands must fit in one workgroup's LDS "
+               "((d+1)*w*8 <= 131072 bytes, w = m doubles per coefficient, 2m for complex series; "
+               "twice that when w <= 2, where both operands are staged)";
     }
     if (d + 1 > 65535) {
         *unsupported = true;

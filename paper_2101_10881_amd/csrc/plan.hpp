@@ -3,6 +3,8 @@
 // hazard check and the lane schedule of the convolution kernel.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <array>
 #include <cstdint>
 #include <string>
@@ -23,6 +25,13 @@ struct LaneSchedule {
     // the lane computes, -1 after its last one.
     std::vector<int32_t> chains;
 };
+
+// The convolution kernel stages both operands of a job in LDS when a
+// coefficient is at most two doubles (short steps: the second operand's
+// latency from L2 would dominate), else only the first.  Doubles of LDS per
+// coefficient of a job:
+__host__ __device__ constexpr bool stages_second_operand(int w) { return w <= 2; }
+__host__ __device__ constexpr int lds_doubles_per_coef(int w) { return stages_second_operand(w) ? 2 * w : w; }
 
 constexpr uint32_t kKeepMonomialValues = 1u;
 constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then imaginary limbs
