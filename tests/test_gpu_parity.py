@@ -128,6 +128,14 @@ def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     _compare(oracle_lib, build(m=m, d=d))
 
 
+@pytest.mark.parametrize("m,d,cx", [(10, 1637, False), (10, 818, True), (1, 8191, False), (2, 4095, False),
+                                     (4, 2000, False)])
+def test_maximum_degrees_bitexact(oracle_lib, m, d, cx):
+    # the largest d whose convolution operands fit one workgroup's LDS (more
+    # than 64 KB of it), for real and complex series and both staging modes
+    _compare(oracle_lib, W.make(f"maxd_m{m}_d{d}", m, d, 3, [(0, 1), (0, 1, 2), (2,)], seed=3, cx=cx))
+
+
 def test_config1_full_size_digest():
     # full-size deca-double p1 at d = 152, in the launch configuration the benchmark times
     g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["config1"]

@@ -303,3 +303,11 @@ def test_exponent_limits(exps, flags, code):
         mdpe.Plan(4, [2], [0, 1], 3, 2, device=-1, flags=flags, exps=exps)
     assert e.value.code == code
     mdpe.Plan(4, [2], [0, 1], 3, 2, device=-1, flags=mdpe.MDPE_KEEP_MONOMIAL_VALUES, exps=[1, 1])
+
+
+@pytest.mark.parametrize("m,d,flags", [(10, 1637, 0), (10, 818, mdpe.MDPE_COMPLEX), (1, 8191, 0), (2, 4095, 0)])
+def test_largest_degrees(m, d, flags):
+    mdpe.Plan(3, [2], [0, 1], d, m, device=-1, flags=flags)
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Plan(3, [2], [0, 1], d + 1, m, device=-1, flags=flags)
+    assert e.value.code == mdpe.MDPE_EUNSUPPORTED
