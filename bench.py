@@ -246,6 +246,42 @@ def measure_complex(steps, warmup, m=10, d=152):
             "conv_TFLOPs": round(conv_f / (cnv * 1e-3) / 1e12, 3)}
 
 
+def measure_streamed(steps, warmup):
+    """Streamed operands (both read from global memory, several wavefronts per
+    job): c1's workload forced to stream (its plan stages), and a large degree
+    (all 4-subsets of 8 variables, quad double, d = 4000) where the plan
+    streams by itself, beside the same plan forced to stage."""
+    import torch
+
+    from paper_2101_10881_amd import flops, mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    big = W.make("p_8_4_4d_d4000", 4, 4000, 8, W.all_subsets(8, 4), seed=1)
+    for key, w, force in (("c1_forced", W.config1(), True), ("degree_4000_staged", big, False),
+                          ("degree_4000", big, None)):
+        P = mdpe.Polynomial.for_workload(w, dev, stream_operands=force)
+        coeff = torch.from_numpy(w.coeff).to(dev)
+        z = torch.from_numpy(w.z).to(dev)
+        v, g = P.eval_and_diff(coeff, z)
+        for _ in range(warmup):
+            P.eval_and_diff(coeff, z, v, g)
+        torch.cuda.synchronize()
+        prof = mdpe.Profiler()
+        for _ in range(steps):
+            P.eval_and_diff(coeff, z, v, g, profiler=prof)
+        t = prof.read()
+        info = P.plan.info
+        cnv = t["cnv_ms"] / steps
+        conv_f = info["n_conv"] * flops.conv_flops(w.m, w.d)
+        out[key] = {"workload": w.name, "streamed": bool(info["streamed"]), "waves_per_job": info["waves_per_job"],
+                    "lane_steps": info["lane_steps"], "cnv_ms": round(cnv, 4),
+                    "conv_TFLOPs": round(conv_f / (cnv * 1e-3) / 1e12, 3)}
+        del P, coeff, z, v, g
+    return out
+
+
 def sweep_workload(poly, m, d, cx=False, emax=1):
     from paper_2101_10881_amd import workloads as W
     w = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
@@ -414,6 +450,7 @@ def main():
         out["batched_vs_plain"] = measure_c3(a.instances, 3, 1)
         out["autograd_c4"] = measure_c4(10, 2)
         out["complex_p1"] = measure_complex(5, 1)
+        out["streamed_operands"] = measure_streamed(3, 1)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -53,7 +53,8 @@ typedef struct {
     const int32_t *nvars;   /* host [N]: n_k, 1 <= n_k <= n */
     const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
                                increasing inside each monomial (Section 4) */
-    uint32_t flags;         /* 0, MDPE_KEEP_MONOMIAL_VALUES or MDPE_COMPLEX */
+    uint32_t flags;         /* 0, or MDPE_KEEP_MONOMIAL_VALUES, MDPE_COMPLEX, MDPE_STREAM_OPERANDS,
+                               MDPE_STAGE_OPERANDS */
     const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
                                (every exponent one).  Monomial k is then
                                a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
@@ -84,6 +85,25 @@ typedef struct {
  * accepted by plan_batch (MDPE_EUNSUPPORTED). */
 #define MDPE_COMPLEX 2u
 
+/* Plan flag: read both convolution operands from global memory (L2) instead
+ * of staging them in LDS.  Plans choose this by themselves when it is
+ * estimated to be faster (few jobs per layer at a large degree), and when a
+ * job's operands would not fit in one workgroup's LDS, i.e. beyond
+ * (d+1)*w*8 > 131072 bytes (w = m doubles per coefficient, 2m complex; twice
+ * that when w <= 2), which lifts the degree limit to d + 1 <= 65535.  Then
+ * one job's coefficients may be spread over several wavefronts
+ * (mdpe_plan_info.waves_per_job), and no convolution writes its own first
+ * operand (the in-place multiplications get fresh output slots).  The
+ * operation order, hence every output bit, is the same as with staged
+ * operands.  plan_batch refuses streamed plans (MDPE_EUNSUPPORTED). */
+#define MDPE_STREAM_OPERANDS 4u
+
+/* Plan flag: stage the operands in LDS even where streaming them is
+ * estimated to be faster (plans otherwise choose by a cost model: few jobs
+ * per layer at a large degree stream, with several wavefronts per job).
+ * MDPE_EUNSUPPORTED when they do not fit; excludes MDPE_STREAM_OPERANDS. */
+#define MDPE_STAGE_OPERANDS 8u
+
 /* Plan summary. */
 typedef struct {
     int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
@@ -99,6 +119,8 @@ typedef struct {
     int64_t n_reverse;      /* correlation jobs of the reverse pass (0 without the flag) */
     uint32_t flags;
     int64_t n_scale;        /* exponent scale jobs (0 for multilinear polynomials) */
+    int32_t waves_per_job;  /* wavefronts sharing one convolution job (streamed operands) */
+    int32_t streamed;       /* 1 if the convolution operands are read from global memory */
 } mdpe_plan_info;
 
 /*

@@ -71,7 +71,7 @@ __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, in
     if (kind == 1) {
         for (int g = 0; g < T.count; g += I.J) {
             conv_group<M, false>(I.A, I.conv + T.first + g, min(I.J, T.count - g), I.J, I.d, lds, I.chains,
-                                 I.stride, I.steps, lane);
+                                 I.stride, I.steps, lane, lane);
             __syncthreads();
         }
     } else {
@@ -282,6 +282,7 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         if (dev != B->device) return bfail(MDPE_EINVAL, "plans on different devices (or host-only mixed in)");
         if (P->complex_series()) return bfail(MDPE_EUNSUPPORTED, "batches hold real series only (MDPE_COMPLEX plan)");
         if (!P->scale.empty()) return bfail(MDPE_EUNSUPPORTED, "batches hold multilinear polynomials only (exponents)");
+        if (P->streamed) return bfail(MDPE_EUNSUPPORTED, "batches stage operands in LDS (streamed-operand plan)");
         if (std::find(ms.begin(), ms.end(), P->m) == ms.end()) ms.push_back(P->m);
     }
     std::sort(ms.begin(), ms.end());

@@ -45,16 +45,21 @@ __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xd
 // coefficients of each spread over the lanes by the schedule `chains`).
 // lds must hold conv_lds_jobs_offset(J*(d+1)*lds_doubles_per_coef(W)) + J*16
 // bytes.  Ends with the wavefront's stores issued (not necessarily complete).
-template <int M, bool CORR, bool CX = false>
+// XS = true (streamed operands, for degrees whose operands do not fit in LDS):
+// both operands are read from global memory and only the job descriptors are
+// in LDS; the planner then guarantees that no job writes its first operand.
+// `row` selects the lane's row of the schedule (q*64 + lane for the q-th of
+// the wavefronts sharing a job).
+template <int M, bool CORR, bool CX = false, bool XS = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
-                                           int steps, int lane) {
+                                           int steps, int lane, int row) {
     constexpr int W = kCoef<M, CX>;
-    constexpr bool YL = stages_second_operand(W);
+    constexpr bool YL = !XS && stages_second_operand(W);
     const long S = (long)(d + 1) * W;
     double *X = lds;
     double *Y = lds + J * S;  // used when YL
-    int4 *jd = (int4 *)((char *)lds + conv_lds_jobs_offset(J * (YL ? 2 : 1) * S));
+    int4 *jd = (int4 *)((char *)lds + (XS ? 0 : conv_lds_jobs_offset(J * (YL ? 2 : 1) * S)));
     // Stage the first operand of every job in LDS: it is read by all lanes and
     // may be the job's own output (the in-place b := b * a of Section 3).  The
     // second operand is never the output (the planner checks) and is streamed
@@ -64,8 +69,10 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     // first operand is read one step ahead of its use, the second two steps.
     for (int j = 0; j < jn; ++j) {
         const int4 t = jobs[j];
-        const double *xs = A + (long)t.x * S;
-        for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+        if (!XS) {
+            const double *xs = A + (long)t.x * S;
+            for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+        }
         if (YL) {
             const double *ys = A + (long)t.y * S;
             for (long q = lane; q < S; q += 64) Y[j * S + q] = ys[q];
@@ -75,7 +82,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     __syncthreads();
     if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barrier)
 
-    const int *my = chains + (long)lane * stride;
+    const int *my = chains + (long)row * stride;
     // Next position in the lane's chain list (reads the -1 terminator at most).
     auto advance = [&](const ChainState &cur, ChainState &nxt, int4 &nj) {
         nxt = cur;
@@ -99,14 +106,18 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     st.code = my[0];
     chain_decode(st, jn);
     int4 job = jd[st.live ? st.j : 0];
+    // the first operand of a position: LDS, or global memory when streamed
+    auto xaddr = [&](const ChainState &t, const int4 &jb) -> const double * {
+        return XS ? A + (long)jb.x * S + (long)xidx(t.k, t.i) * W : X + t.j * S + xidx(t.k, t.i) * W;
+    };
     double p[W];
     {
-        const double *xp = X + st.j * S + xidx(st.k, 0) * W;
+        const double *xp = xaddr(st, job);
         const double *yp = YL ? Y + st.j * S + yidx(st.k, 0) * W : A + (long)job.y * S + (long)yidx(st.k, 0) * W;
         double x0[W], y0[W];
 #pragma unroll
         for (int l = 0; l < W; ++l) {
-            x0[l] = xp[l];
+            x0[l] = XS ? (st.live ? xp[l] : 0.0) : xp[l];
             y0[l] = st.live ? yp[l] : 0.0;
         }
         coef_mul<M, CX>(x0, y0, p);
@@ -114,12 +125,17 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     ChainState nx;
     int4 njob = job;
     advance(st, nx, njob);
-    double yn[W];
+    double yn[W], xn[W];
     {
         const double *yp = YL ? Y + nx.j * S + yidx(nx.k, nx.i) * W : A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * W;
         const bool fetch = nx.live && 1 < steps;
 #pragma unroll
         for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
+        if (XS) {  // streamed: x is read two steps ahead too
+            const double *xp = xaddr(nx, njob);
+#pragma unroll
+            for (int l = 0; l < W; ++l) xn[l] = fetch ? xp[l] : 0.0;
+        }
     }
     double acc[W];
 #pragma unroll
@@ -132,10 +148,19 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 #pragma unroll
         for (int l = 0; l < W; ++l) y1[l] = yn[l];
         {
-            const double *xp = X + nx.j * S + xidx(nx.k, nx.i) * W;
-#pragma unroll
-            for (int l = 0; l < W; ++l) x1[l] = xp[l];
             const bool fetch = n2.live && s + 2 < steps;
+            if (XS) {
+                const double *xp = xaddr(n2, n2job);
+#pragma unroll
+                for (int l = 0; l < W; ++l) {
+                    x1[l] = xn[l];
+                    xn[l] = fetch ? xp[l] : 0.0;
+                }
+            } else {
+                const double *xp = xaddr(nx, njob);
+#pragma unroll
+                for (int l = 0; l < W; ++l) x1[l] = xp[l];
+            }
             const double *yp = YL ? Y + n2.j * S + yidx(n2.k, n2.i) * W
                                   : A + (long)n2job.y * S + (long)yidx(n2.k, n2.i) * W;
 #pragma unroll
@@ -167,15 +192,21 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 // between one and three wavefronts per SIMD, where single-wavefront workgroups
 // can pile three onto one SIMD while another stays idle.  (A separate
 // instantiation: the 256-thread launch bound alone slows a lone wavefront.)
-template <int M, bool CORR, bool CX = false, int WPB = 1>
+// Streamed operands (XS): Q wavefronts share each group; wavefront w takes
+// group w / Q, schedule part w % Q.
+template <int M, bool CORR, bool CX = false, int WPB = 1, bool XS = false>
 __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                               int njobs, int d, int J, const int *__restrict__ chains,
-                                                              int stride, int steps, int group_bytes) {
+                                                              int stride, int steps, int group_bytes, int Q) {
     extern __shared__ double lds[];
     const int wave = WPB == 1 ? 0 : (int)(threadIdx.x >> 6);
-    const int g0 = (blockIdx.x * WPB + wave) * J;
-    conv_group<M, CORR, CX>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
-                            chains, stride, steps, threadIdx.x & 63);
+    const int wv = blockIdx.x * WPB + wave;
+    const int g = XS ? wv / Q : wv;
+    const int part = XS ? wv - g * Q : 0;
+    const int g0 = g * J;
+    const int lane = threadIdx.x & 63;
+    conv_group<M, CORR, CX, XS>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
+                                chains, stride, steps, lane, part * 64 + lane);
 }
 
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).

@@ -159,8 +159,7 @@ namespace {
 
 using mdpe::g_err;
 
-size_t conv_lds_bytes(int d, int m, int J, int stride) {
-    (void)stride;
+size_t conv_lds_bytes(int d, int m, int J) {
     return (size_t)mdpe::conv_lds_jobs_offset((long)J * (d + 1) * m) + (size_t)J * sizeof(int4);
 }
 
@@ -265,30 +264,44 @@ template <int M, bool CORR, bool CX>
 int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
-    const size_t group_bytes =
-        (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J, P.lanes.stride) + 15) / 16 * 16;
+    const int Q = P.lanes.waves_per_job;
     static bool attr_set = false;
     if (!attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1>,
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
-        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4>,
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set = true;
     }
     if (nj == 0) return MDPE_OK;
     const int groups = (nj + J - 1) / J;
-    // one wavefront per workgroup, or one per SIMD (see conv_layer_kernel)
-    const int simds = simd_count(pl->device);
-    const int wpb = (groups > simds && groups <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
-    const int blocks = (groups + wpb - 1) / wpb;
     int rc = record(prof, 1, st, true);
     if (rc) return rc;
-    if (wpb == 4)
-        hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4>), dim3(blocks), dim3(256), 4 * group_bytes, st, A,
-                           jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps, (int)group_bytes);
-    else
-        hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1>), dim3(blocks), dim3(64), group_bytes, st, A,
-                           jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps, (int)group_bytes);
+    if (P.streamed) {
+        // operands from global memory; only the job descriptors are in LDS
+        const size_t group_bytes = conv_lds_bytes(P.d, 0, J);
+        const long waves = (long)groups * Q;
+        if (waves > 0x7fffffffL) return fail(MDPE_EUNSUPPORTED, "too many wavefronts in one layer");
+        hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, true>), dim3((unsigned)waves), dim3(64),
+                           group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
+                           (int)group_bytes, Q);
+    } else {
+        const size_t group_bytes =
+            (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
+        // one wavefront per workgroup, or one per SIMD (see conv_layer_kernel)
+        const int simds = simd_count(pl->device);
+        const int wpb =
+            (groups > simds && groups <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
+        const int blocks = (groups + wpb - 1) / wpb;
+        if (wpb == 4)
+            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false>), dim3(blocks), dim3(256),
+                               4 * group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
+                               (int)group_bytes, 1);
+        else
+            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false>), dim3(blocks), dim3(64), group_bytes,
+                               st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
+                               (int)group_bytes, 1);
+    }
     LAUNCH_CHECK("conv_layer_kernel");
     return record(prof, 1, st, false);
 }
@@ -453,7 +466,8 @@ extern "C" {
 int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
-    if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX)) return fail(MDPE_EINVAL, "unknown flags");
+    if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS))
+        return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
     if (!pl) return fail(MDPE_ENOMEM, "host allocation failed");
@@ -518,6 +532,8 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->lane_steps = P.lanes.steps;
     o->n_reverse = (int64_t)P.corr.size();
     o->n_scale = (int64_t)P.scale.size();
+    o->waves_per_job = P.lanes.waves_per_job;
+    o->streamed = P.streamed ? 1 : 0;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;

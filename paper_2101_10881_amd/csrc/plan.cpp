@@ -20,6 +20,8 @@
 // recursion, read through the worked example after eq. (5)).
 #include "plan.hpp"
 
+#include <cmath>
+
 #include <algorithm>
 #include <numeric>
 #include <unordered_map>
@@ -39,14 +41,16 @@ int choose_jobs_per_group(int d, int w) {
     return (int)std::max(1L, std::min((long)need, cap));
 }
 
-LaneSchedule make_lane_schedule(int d, int J) {
+LaneSchedule make_lane_schedule(int d, int J, int Q) {
     // Assign the J*(d+1) output coefficients (coefficient k costs k+1
-    // multiply-adds) to 64 lanes: first-fit-decreasing into lanes of capacity
-    // C, for the smallest C >= max(ceil(total/64), d+1) that fits.  Each
-    // coefficient stays whole on one lane, so its operation order is the
-    // specified one whatever lane computes it.
+    // multiply-adds) to the 64*Q lanes of Q wavefronts: first-fit-decreasing
+    // into lanes of capacity C, for the smallest C >= max(ceil(total/lanes),
+    // d+1) that fits.  Each coefficient stays whole on one lane, so its
+    // operation order is the specified one whatever lane computes it.
     LaneSchedule s;
     s.jobs_per_group = J;
+    s.waves_per_job = Q;
+    const int lanes = kLanes * Q;
     std::vector<std::pair<int, int>> items;  // (length, code)
     long total = 0;
     for (int j = 0; j < J; ++j)
@@ -57,14 +61,14 @@ LaneSchedule make_lane_schedule(int d, int J) {
     std::stable_sort(items.begin(), items.end(), [](auto &a, auto &b) { return a.first > b.first; });
     std::vector<long> load;
     std::vector<std::vector<int32_t>> lists;
-    for (long cap = std::max((total + kLanes - 1) / kLanes, (long)d + 1);; ++cap) {
-        load.assign(kLanes, 0);
-        lists.assign(kLanes, {});
+    for (long cap = std::max((total + lanes - 1) / lanes, (long)d + 1);; ++cap) {
+        load.assign(lanes, 0);
+        lists.assign(lanes, {});
         bool ok = true;
         for (auto &it : items) {
             int l = 0;
-            while (l < kLanes && load[l] + it.first > cap) ++l;
-            if (l == kLanes) {
+            while (l < lanes && load[l] + it.first > cap) ++l;
+            if (l == lanes) {
                 ok = false;
                 break;
             }
@@ -77,10 +81,38 @@ LaneSchedule make_lane_schedule(int d, int J) {
     for (auto &l : lists) stride = std::max(stride, l.size() + 1);
     s.stride = (int)stride;
     s.steps = (int)*std::max_element(load.begin(), load.end());
-    s.chains.assign((size_t)kLanes * stride, -1);
-    for (int l = 0; l < kLanes; ++l)
+    s.chains.assign((size_t)lanes * stride, -1);
+    for (int l = 0; l < lanes; ++l)
         for (size_t q = 0; q < lists[l].size(); ++q) s.chains[(size_t)l * stride + q] = lists[l][q];
     return s;
+}
+
+LaneSchedule make_paired_schedule(int d, int Q) {
+    // One job over the 64*Q lanes of Q wavefronts for large d: coefficients k
+    // and d-k (k+1 and d-k+1 terms, d+2 together) share a lane, one pair per
+    // lane; the middle coefficient of an even d is alone.  Q*64 must be at
+    // least the number of pairs, ceil((d+1)/2).
+    LaneSchedule s;
+    s.jobs_per_group = 1;
+    s.waves_per_job = Q;
+    const int lanes = kLanes * Q;
+    s.stride = 3;
+    s.chains.assign((size_t)lanes * 3, -1);
+    int steps = 0;
+    for (int k = 0, l = 0; k <= d - k; ++k, ++l) {
+        s.chains[(size_t)l * 3] = d - k;                    // the longer coefficient first
+        if (k != d - k) s.chains[(size_t)l * 3 + 1] = k;
+        steps = std::max(steps, (d - k + 1) + (k != d - k ? k + 1 : 0));
+    }
+    s.steps = steps;
+    return s;
+}
+
+int stream_waves_per_job(int d, bool *paired) {
+    const int pairs = (d + 2) / 2;
+    *paired = d + 1 > 4096;
+    if (*paired) return (pairs + kLanes - 1) / kLanes;
+    return std::max(1, pairs / kLanes);
 }
 
 // Pairwise tree over `items`; pushes the jobs of round r into rounds[r].
@@ -117,6 +149,7 @@ static std::string check_hazards(const Plan &P) {
             // written, so it may never be the job's own output
             const bool conv_stage = stage <= P.n_layers() || stage > P.n_layers() + 1 + P.n_levels();
             if (conv_stage && jobs[q][1] == w) return "second operand is the output";
+            if (conv_stage && P.streamed && jobs[q][0] == w) return "first operand is the output (streamed)";
             if (w < 0 || w >= P.n_series) return "slot out of range";
             if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
         }
@@ -163,10 +196,44 @@ static std::string check_hazards(const Plan &P) {
     return "";
 }
 
+static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
+                                   const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported);
+
+// Relative cost of a layer plan: each layer takes about ceil(wavefronts /
+// SIMDs) wavefront lifetimes (a SIMD's throughput hardly depends on how many
+// wavefronts share it), a streamed step costing ~1.2 staged steps (c1: 15.2
+// vs 12.9 ms at equal steps).
+static double layer_cost(const Plan &P, int waves_per_job, int jobs_per_group, int steps, double step_cost) {
+    constexpr double kSimds = 1024.0;  // MI355X: 256 CUs x 4 SIMDs
+    double c = 0;
+    for (int L = 1; L <= P.n_layers(); ++L) {
+        const long jobs = P.conv_off[L] - P.conv_off[L - 1];
+        const long waves = (jobs + jobs_per_group - 1) / jobs_per_group * waves_per_job;
+        c += std::ceil(waves / kSimds) * steps * step_cost;
+    }
+    return c;
+}
+
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
                        uint32_t flags, Plan &P, bool *unsupported) {
+    // Staged operands unless asked otherwise, or unless they do not fit in
+    // LDS, or unless streaming with several wavefronts per job is estimated
+    // to be faster (large d with few jobs per layer).
+    std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, P, unsupported);
+    if (!err.empty() || P.streamed || (flags & kStageOperands)) return err;
+    bool paired = false;
+    const int Q = stream_waves_per_job(d, &paired);
+    if (Q < 2) return err;
+    const LaneSchedule ss = paired ? make_paired_schedule(d, Q) : make_lane_schedule(d, 1, Q);
+    if (layer_cost(P, Q, 1, ss.steps, 1.2) >= layer_cost(P, 1, P.lanes.jobs_per_group, P.lanes.steps, 1.0)) return err;
+    return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, true, P, unsupported);
+}
+
+static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
+                                   const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported) {
     *unsupported = false;
-    if (flags & ~(kKeepMonomialValues | kComplex)) return "unknown flags";
+    if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands)) return "unknown flags";
+    if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;
     const bool cx = (flags & kComplex) != 0;
     if (keep && cx) {
@@ -227,17 +294,30 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     const int64_t pbase = base + tot + nb + nc;  // powers, then common factors
     const int64_t fbase = pbase + npow;
     const int64_t mbase = fbase + nfac;
-    const int64_t nser = mbase + (keep ? nmono2 + 1 + N + n : 0);
+    const int w = cx ? 2 * m : m;
+    // Streamed operands when a job's LDS operands would not fit in one
+    // workgroup's LDS, or when asked for.  Then no convolution may write its
+    // own first operand: b_{n-2} * a and every common-factor step after the
+    // first get fresh output slots, after all others.
+    const bool fits = (long)(d + 1) * lds_doubles_per_coef(w) * 8 <= kMaxLdsBytes - 32768;
+    if ((flags & kStageOperands) && !fits) {
+        *unsupported = true;
+        return "MDPE_STAGE_OPERANDS: a job's operands do not fit in one workgroup's LDS "
+               "((d+1)*w*8 <= 131072 bytes, w = m doubles per coefficient, 2m complex; twice that when w <= 2)";
+    }
+    const bool streamed = stream || (flags & kStreamOperands) || !fits;
+    int64_t n3 = 0, nfac_extra = 0;
+    for (int k = 0, q = 0; k < N; q += nvars[k], ++k) {
+        n3 += nvars[k] >= 3;
+        int cnt = 0;
+        for (int j = 0; exps && j < nvars[k]; ++j) cnt += exps[q + j] >= 2;
+        nfac_extra += std::max(0, cnt - 1);
+    }
+    const int64_t xbase = mbase + (keep ? nmono2 + 1 + N + n : 0);
+    const int64_t nser = xbase + (streamed ? n3 + nfac_extra : 0);
     if (nser > INT32_MAX / 2) {
         *unsupported = true;
         return "too many series for 32-bit slot indices";
-    }
-    const int w = cx ? 2 * m : m;
-    if ((long)(d + 1) * lds_doubles_per_coef(w) * 8 > kMaxLdsBytes - 32768) {
-        *unsupported = true;
-        return "d too large: a convolution job's LDS operands must fit in one workgroup's LDS "
-               "((d+1)*w*8 <= 131072 bytes, w = m doubles per coefficient, 2m for complex series; "
-               "twice that when w <= 2, where both operands are staged)";
     }
     if (d + 1 > 65535) {
         *unsupported = true;
@@ -251,6 +331,9 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     P.w = w;
     P.flags = flags;
     P.n_series = nser;
+    P.streamed = streamed;
+    int64_t xpos = 0;
+    auto fresh = [&]() { return (int32_t)(xbase + xpos++); };
 
     std::vector<std::vector<std::array<int32_t, 3>>> layers(std::max(nmax, 1));
     auto add_job = [&](int layer, int32_t t1, int32_t t2, int32_t t3) {
@@ -280,7 +363,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         int shift = 0;
         for (int j = 0; e && j < nk; ++j) {
             if (e[j] < 2) continue;
-            const int32_t fac = (int32_t)(fbase + fpos);
+            const int32_t fac = streamed && a_slot != (int32_t)(k + 1) ? fresh() : (int32_t)(fbase + fpos);
             const int ready = e[j] - 1 >= 2 ? e[j] - 2 : 0;
             shift = std::max(shift, ready) + 1;
             add_job(shift, a_slot, pow_slot(v[j], e[j] - 1), fac);
@@ -322,21 +405,23 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
             } else {
                 job(1, Z(nk), Z(nk - 1), B(1));
                 for (int j = 2; j <= nk - 2; ++j) job(j, B(j - 1), Z(nk - j), B(j));
+                // b_{n-2} := b_{n-2} * a_k, in place unless operands are streamed
+                const int32_t bfin = streamed ? fresh() : B(nk - 2);
                 if (keep) {
                     // M_k = b_{n-2} * z_{i_1} reads the backward product before its
                     // multiplication by a_k, which therefore moves one layer later
                     mono_slot[k] = (int32_t)(mbase + mpos++);
                     job(nk - 1, B(nk - 2), Z(1), mono_slot[k]);
-                    job(nk, B(nk - 2), A(), B(nk - 2));
+                    job(nk, B(nk - 2), A(), bfin);
                 } else {
-                    job(nk - 1, B(nk - 2), A(), B(nk - 2));
+                    job(nk - 1, B(nk - 2), A(), bfin);
                 }
                 for (int j = 1; j <= nk - 3; ++j) job(std::max(j, nk - 2 - j) + 1, F(j), B(nk - 2 - j), C(j));
                 job(nk - 1, F(nk - 2), Z(nk), C(nk - 2));
-                grad_lists[v[0]].push_back(B(nk - 2));
+                grad_lists[v[0]].push_back(bfin);
                 for (int j = 1; j <= nk - 2; ++j) grad_lists[v[j]].push_back(C(j));
                 grad_lists[v[nk - 1]].push_back(F(nk - 1));
-                scale(0, B(nk - 2), B(nk - 2));
+                scale(0, bfin, bfin);
                 for (int j = 1; j <= nk - 2; ++j) scale(j, C(j), C(j));
                 scale(nk - 1, F(nk - 1), F(nk - 1));
             }
@@ -385,7 +470,17 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     auto err = check_hazards(P);
     if (!err.empty()) return "internal planner error: " + err;
 
-    P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, w));
+    if (xpos != nser - xbase) return "internal planner error: fresh slot count";
+    if (streamed) {
+        bool paired = false;
+        const int Q = stream_waves_per_job(d, &paired);
+        if (paired)
+            P.lanes = make_paired_schedule(d, Q);
+        else
+            P.lanes = make_lane_schedule(d, Q > 1 ? 1 : std::max(1, std::min(kLanes, (2 * kLanes + d + 1) / (d + 2))), Q);
+    } else {
+        P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, w));
+    }
     return "";
 }
 

@@ -19,10 +19,12 @@ constexpr int kMaxExponent = 64;
 
 struct LaneSchedule {
     int jobs_per_group = 1;            // J: convolution jobs staged per workgroup
+    int waves_per_job = 1;             // Q: wavefronts sharing one job's coefficients (J = 1 when Q > 1)
     int steps = 0;                     // multiply-add steps of the busiest lane
     int stride = 0;                    // entries per lane in `chains`
-    // chains[lane*stride + s]: (job << 16) | k for the s-th output coefficient
-    // the lane computes, -1 after its last one.
+    // chains[row*stride + s]: (job << 16) | k for the s-th output coefficient
+    // schedule row `row` computes, -1 after its last one; row q*64 + lane is
+    // lane `lane` of the q-th of the Q wavefronts of a group.
     std::vector<int32_t> chains;
 };
 
@@ -35,6 +37,8 @@ __host__ __device__ constexpr int lds_doubles_per_coef(int w) { return stages_se
 
 constexpr uint32_t kKeepMonomialValues = 1u;
 constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then imaginary limbs
+constexpr uint32_t kStreamOperands = 4u;   // read both convolution operands from global memory
+constexpr uint32_t kStageOperands = 8u;    // stage them in LDS (no automatic streaming)
 
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
@@ -63,6 +67,9 @@ struct Plan {
     std::vector<int32_t> z_bar_slots;       // [n]: zbar_i slot or -1 (absent variable)
 
     bool complex_series() const { return (flags & kComplex) != 0; }
+    // streamed operands: chosen when a job's operands would not fit in LDS, or
+    // asked for; then no convolution writes its own first operand
+    bool streamed = false;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };
@@ -73,7 +80,11 @@ struct Plan {
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
                        uint32_t flags, Plan &out, bool *unsupported);
 
-LaneSchedule make_lane_schedule(int d, int jobs_per_group);
+LaneSchedule make_lane_schedule(int d, int jobs_per_group, int waves_per_job = 1);
+LaneSchedule make_paired_schedule(int d, int waves_per_job);
+// Streamed operands: wavefronts per job for degree d, and whether the paired
+// schedule is used (large d, where first-fit would be slow to build).
+int stream_waves_per_job(int d, bool *paired);
 int choose_jobs_per_group(int d, int w);
 
 }  // namespace mdpe

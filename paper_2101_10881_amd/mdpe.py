@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mdpe.h")
 MDPE_OK, MDPE_EINVAL, MDPE_EUNSUPPORTED, MDPE_ENOMEM, MDPE_EDEVICE = 0, -1, -2, -3, -4
 MDPE_KEEP_MONOMIAL_VALUES = 1
 MDPE_COMPLEX = 2
+MDPE_STREAM_OPERANDS = 4
+MDPE_STAGE_OPERANDS = 8
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -42,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_layers", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("jobs_per_group", ctypes.c_int32), ("lane_steps", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64)]
+                ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64),
+                ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -287,12 +290,16 @@ class Polynomial:
     exps: one exponent per entry of vars_ (None: every exponent one).
     """
 
-    def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None):
+    def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
+                 stream_operands=None):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
-        flags = (MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0) | (MDPE_COMPLEX if complex else 0)
+        # stream_operands: None lets the plan choose, True / False forces it
+        flags = ((MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0) | (MDPE_COMPLEX if complex else 0) |
+                 (MDPE_STREAM_OPERANDS if stream_operands is True else 0) |
+                 (MDPE_STAGE_OPERANDS if stream_operands is False else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)
@@ -302,9 +309,9 @@ class Polynomial:
         self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
 
     @classmethod
-    def for_workload(cls, w, device=None, keep_monomials=False):
+    def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
-                   getattr(w, "exps", None))
+                   getattr(w, "exps", None), stream_operands)
 
     def new_workspace(self):
         import torch

@@ -132,8 +132,18 @@ def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
                                      (4, 2000, False)])
 def test_maximum_degrees_bitexact(oracle_lib, m, d, cx):
     # the largest d whose convolution operands fit one workgroup's LDS (more
-    # than 64 KB of it), for real and complex series and both staging modes
-    _compare(oracle_lib, W.make(f"maxd_m{m}_d{d}", m, d, 3, [(0, 1), (0, 1, 2), (2,)], seed=3, cx=cx))
+    # than 64 KB of it), staged there on request, for real and complex series
+    # and both staging modes
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = W.make(f"maxd_m{m}_d{d}", m, d, 3, [(0, 1), (0, 1, 2), (2,)], seed=3, cx=cx)
+    P = mdpe.Polynomial.for_workload(w, torch.device("cuda", 0), stream_operands=False)
+    assert not P.plan.info["streamed"]
+    _say(f"eval_and_diff {w.name}: staged at the LDS limit")
+    want_v, want_g = oracle_lib.eval_workload(w)
+    got_v, got_g = run_gpu(w, poly=P)
+    assert_bitexact(got_v, want_v, f"{w.name} value")
+    assert_bitexact(got_g, want_g, f"{w.name} gradient")
 
 
 def test_config1_full_size_digest():

@@ -172,7 +172,7 @@ def test_lane_schedule_is_balanced(cfg):
     (dict(nvars=[2], vars_=[2, 1]), mdpe.MDPE_EINVAL),
     (dict(d=-1), mdpe.MDPE_EINVAL),
     (dict(m=6), mdpe.MDPE_EUNSUPPORTED),
-    (dict(m=10, d=2000), mdpe.MDPE_EUNSUPPORTED),                  # one operand series exceeds LDS
+    (dict(m=10, d=65535), mdpe.MDPE_EUNSUPPORTED),                 # beyond the 16-bit coefficient index
 ])
 def test_invalid_descriptions(bad, code):
     args = dict(n=4, nvars=[2], vars_=[0, 1], d=3, m=2)
@@ -247,15 +247,18 @@ def test_complex_plan_same_jobs_double_workspace():
 
 @pytest.mark.parametrize("flags, m, d, code", [
     (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
-    (mdpe.MDPE_COMPLEX, 10, 819, mdpe.MDPE_EUNSUPPORTED),   # (d+1)*2m*8 > 131072
-    (4, 2, 3, mdpe.MDPE_EINVAL),                             # unknown flag
+    (16, 2, 3, mdpe.MDPE_EINVAL),                            # unknown flag
+    (mdpe.MDPE_STREAM_OPERANDS | mdpe.MDPE_STAGE_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
+    (mdpe.MDPE_STAGE_OPERANDS, 10, 1700, mdpe.MDPE_EUNSUPPORTED),  # does not fit in LDS
 ])
 def test_complex_plan_limits(flags, m, d, code):
     with pytest.raises(mdpe.MdpeError) as e:
         mdpe.Plan(4, [2], [0, 1], d, m, device=-1, flags=flags)
     assert e.value.code == code
-    mdpe.Plan(4, [2], [0, 1], 818, 10, device=-1, flags=mdpe.MDPE_COMPLEX)      # the largest complex d at m = 10
-    mdpe.Plan(4, [2], [0, 1], 819, 10, device=-1)                               # still fine when real
+    many = dict(nvars=[2] * 5000, vars_=[0, 1] * 5000)      # layers big enough that staging pays
+    assert not mdpe.Plan(4, many["nvars"], many["vars_"], 818, 10, device=-1, flags=mdpe.MDPE_COMPLEX).info["streamed"]
+    assert mdpe.Plan(4, many["nvars"], many["vars_"], 819, 10, device=-1, flags=mdpe.MDPE_COMPLEX).info["streamed"]
+    assert not mdpe.Plan(4, many["nvars"], many["vars_"], 819, 10, device=-1).info["streamed"]   # real: staged
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -306,8 +309,63 @@ def test_exponent_limits(exps, flags, code):
 
 
 @pytest.mark.parametrize("m,d,flags", [(10, 1637, 0), (10, 818, mdpe.MDPE_COMPLEX), (1, 8191, 0), (2, 4095, 0)])
-def test_largest_degrees(m, d, flags):
-    mdpe.Plan(3, [2], [0, 1], d, m, device=-1, flags=flags)
+def test_largest_staged_degrees(m, d, flags):
+    # the largest d with operands staged in LDS (for layers big enough that
+    # staging pays); one more must stream them
+    nv, vs = [2] * 5000, [0, 1] * 5000
+    p = mdpe.Plan(3, nv, vs, d, m, device=-1, flags=flags)
+    q = mdpe.Plan(3, nv, vs, d + 1, m, device=-1, flags=flags)
+    assert not p.info["streamed"] and q.info["streamed"]
+    pairs = (d + 3) // 2                                  # coefficients k, d-k of degree d+1
+    want = -(-pairs // 64) if d + 2 > 4096 else max(1, pairs // 64)
+    assert q.info["waves_per_job"] == want
+
+
+def test_degree_limit():
+    p = mdpe.Plan(2, [2], [0, 1], 65534, 1, device=-1)
+    assert p.info["streamed"] and p.info["waves_per_job"] == (65536 // 2 + 63) // 64
+    assert p.info["lane_steps"] == 65536                 # one pair (k, d-k) per lane: d + 2 terms
     with pytest.raises(mdpe.MdpeError) as e:
-        mdpe.Plan(3, [2], [0, 1], d + 1, m, device=-1, flags=flags)
+        mdpe.Plan(2, [2], [0, 1], 65535, 1, device=-1)
     assert e.value.code == mdpe.MDPE_EUNSUPPORTED
+
+
+def _streamed_slots_are_fresh(p):
+    rows = p.conv_jobs()
+    return all(t1 != t3 for _, t1, t2, t3 in rows)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_streamed_plan_jobs_compute_the_definition(seed):
+    """Streamed operands: no convolution writes its first operand, and the jobs,
+    run in exact arithmetic, still give the value and gradient (with exponents)."""
+    rng = np.random.default_rng(240 + seed)
+    n = int(rng.integers(1, 7))
+    N = int(rng.integers(1, 7))
+    w = W.random_poly("stream", 1, 3, n, N, rng.integers(1, n + 1, size=N), seed)
+    if seed % 2:
+        w = W.with_exponents(w, 4, seed=seed)
+    p = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_STREAM_OPERANDS)
+    p0 = mdpe.Plan.for_workload(w, device=-1)
+    assert p.info["streamed"] and not p0.info["streamed"]
+    assert _streamed_slots_are_fresh(p)
+    assert p.info["n_conv"] == p0.info["n_conv"] and p.info["n_layers"] == p0.info["n_layers"]
+    val, grad = _execute_exact(p, w)
+    (ev, eg), _ = E.workload_exact(w)
+    assert val == ev and grad == eg
+
+
+def test_streamed_keep_monomials_plan():
+    w = W.random_poly("stream_keep", 1, 2, 6, 7, [1, 2, 3, 4, 5, 6, 3], seed=3)
+    p = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_STREAM_OPERANDS | mdpe.MDPE_KEEP_MONOMIAL_VALUES)
+    assert _streamed_slots_are_fresh(p)
+    assert p.info["n_reverse"] == mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_KEEP_MONOMIAL_VALUES).info["n_reverse"]
+
+
+def test_streaming_chosen_by_cost():
+    # few jobs per layer at a large degree: several wavefronts per job pay
+    big = W.make("big", 4, 4000, 8, W.all_subsets(8, 4), seed=1)
+    p = mdpe.Plan.for_workload(big, device=-1)
+    assert p.info["streamed"] and p.info["waves_per_job"] == 31
+    # c1: thousands of jobs per layer, staged
+    assert not mdpe.Plan.for_workload(W.config1(), device=-1).info["streamed"]
