@@ -187,3 +187,42 @@ def test_profiled_and_side_stream(oracle_lib):
     want_v, want_g = oracle_lib.eval_workload(w)
     assert_bitexact(got[0], want_v, "value")
     assert_bitexact(got[1], want_g, "grad")
+
+
+def test_hip_graph_capture_and_replay(oracle_lib):
+    # the plain path launches kernels only (no allocation, no memset, no
+    # synchronisation), so a caller can capture it in a HIP graph; every
+    # replay, with new inputs copied in and eager work in between, must match
+    # the oracle bit for bit
+    import torch
+    from paper_2101_10881_amd import mdpe
+    dev = torch.device("cuda", 0)
+    w = W.random_poly("graph", 4, 20, 7, 25, np.random.default_rng(21).integers(1, 6, size=25), seed=21)
+    P = mdpe.Polynomial.for_workload(w, dev)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    value = torch.empty((w.m, w.d + 1), dtype=torch.float64, device=dev)
+    grad = torch.empty((w.m, w.n, w.d + 1), dtype=torch.float64, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.eval_and_diff(coeff, z, value, grad)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.eval_and_diff(coeff, z, value, grad)
+    other = W.random_poly("eager", 3, 9, 5, 8, [2] * 8, seed=4)
+    for rep in range(4):
+        _say(f"graph replay {rep}")
+        rng = np.random.default_rng(600 + rep)
+        w.coeff = W.md_series(rng, w.N + 1, w.m, w.d)
+        w.z = W.md_series(rng, w.n, w.m, w.d)
+        coeff.copy_(torch.from_numpy(w.coeff))
+        z.copy_(torch.from_numpy(w.z))
+        graph.replay()
+        run_gpu(other)                       # eager work between replays
+        torch.cuda.synchronize()
+        want_v, want_g = oracle_lib.eval_workload(w)
+        assert_bitexact(value.cpu().numpy(), want_v, f"replay {rep} value")
+        assert_bitexact(grad.cpu().numpy(), want_g, f"replay {rep} gradient")
