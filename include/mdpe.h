@@ -121,6 +121,8 @@ typedef struct {
     int64_t n_scale;        /* exponent scale jobs (0 for multilinear polynomials) */
     int32_t waves_per_job;  /* wavefronts sharing one convolution job (streamed operands) */
     int32_t streamed;       /* 1 if the convolution operands are read from global memory */
+    int32_t simple_dealing; /* 1 if coefficients (of at most two doubles) are dealt to lanes in turn
+                               instead of following the lane schedule */
 } mdpe_plan_info;
 
 /*

@@ -47,6 +47,7 @@ struct BatchInst {
     const int *out;
     const int *chains;
     int stride, steps, J;
+    int simple;  // deal coefficients to lanes in turn (see conv_group)
     int m, d, n, N;
 };
 
@@ -71,7 +72,7 @@ __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, in
     if (kind == 1) {
         for (int g = 0; g < T.count; g += I.J) {
             conv_group<M, false>(I.A, I.conv + T.first + g, min(I.J, T.count - g), I.J, I.d, lds, I.chains,
-                                 I.stride, I.steps, lane, lane);
+                                 I.stride, I.steps, lane, lane, I.simple != 0);
             __syncthreads();
         }
     } else {
@@ -360,6 +361,7 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         I.stride = S.stride;
         I.steps = S.steps;
         I.J = J;
+        I.simple = mdpe::prefer_simple_dealing(P.d, J, P.m, S.steps) ? 1 : 0;
         I.m = P.m;
         I.d = P.d;
         I.n = P.n;

@@ -49,11 +49,13 @@ __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xd
 // both operands are read from global memory and only the job descriptors are
 // in LDS; the planner then guarantees that no job writes its first operand.
 // `row` selects the lane's row of the schedule (q*64 + lane for the q-th of
-// the wavefronts sharing a job).
+// the wavefronts sharing a job).  `simple` (coefficients of at most two
+// doubles, staged operands): deal the coefficients to the lanes in turn
+// instead of following the schedule (see below).
 template <int M, bool CORR, bool CX = false, bool XS = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
-                                           int steps, int lane, int row) {
+                                           int steps, int lane, int row, bool simple = false) {
     constexpr int W = kCoef<M, CX>;
     constexpr bool YL = !XS && stages_second_operand(W);
     const long S = (long)(d + 1) * W;
@@ -81,6 +83,46 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     }
     __syncthreads();
     if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barrier)
+
+    if constexpr (W <= 2 && !XS) {
+        if (simple) {
+            // Coefficients of one or two doubles: a multiply-add is a handful of
+            // operations, so the lane schedule's bookkeeping can dominate.
+            // Instead the group's (job, coefficient) items are dealt to the
+            // lanes in turn and each lane sums its coefficient's terms in the
+            // specified order from the staged operands: more lane-steps, far
+            // fewer instructions per step (the planner weighs the two).
+            const int d1 = d + 1;
+            for (int t = lane; t < jn * d1; t += 64) {
+                const int j = t / d1;
+                const int k = t - j * d1;
+                const double *x = X + (long)j * S;
+                const double *y = Y + (long)j * S;
+                double *out = A + (long)jd[j].z * S + (long)(CORR ? d - k : k) * W;
+                // CORR: z_s = sum_{i=0..d-s} x_{s+i} y_i with s = d - k (k+1 terms)
+                const int x0 = CORR ? d - k : 0;
+                double acc[W], pr[W], xa[W], ya[W];
+#pragma unroll
+                for (int l = 0; l < W; ++l) {
+                    xa[l] = x[x0 * W + l];
+                    ya[l] = y[(CORR ? 0 : k) * W + l];
+                }
+                coef_mul<M, CX>(xa, ya, acc);
+                for (int i = 1; i <= k; ++i) {
+#pragma unroll
+                    for (int l = 0; l < W; ++l) {
+                        xa[l] = x[(x0 + i) * W + l];
+                        ya[l] = y[(CORR ? i : k - i) * W + l];
+                    }
+                    coef_mul<M, CX>(xa, ya, pr);
+                    coef_add<M, CX>(acc, pr, acc);
+                }
+#pragma unroll
+                for (int l = 0; l < W; ++l) out[l] = acc[l];
+            }
+            return;
+        }
+    }
 
     const int *my = chains + (long)row * stride;
     // Next position in the lane's chain list (reads the -1 terminator at most).
@@ -197,7 +239,8 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 template <int M, bool CORR, bool CX = false, int WPB = 1, bool XS = false>
 __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                               int njobs, int d, int J, const int *__restrict__ chains,
-                                                              int stride, int steps, int group_bytes, int Q) {
+                                                              int stride, int steps, int group_bytes, int Q,
+                                                              int simple) {
     extern __shared__ double lds[];
     const int wave = WPB == 1 ? 0 : (int)(threadIdx.x >> 6);
     const int wv = blockIdx.x * WPB + wave;
@@ -206,7 +249,7 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
     const int g0 = g * J;
     const int lane = threadIdx.x & 63;
     conv_group<M, CORR, CX, XS>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
-                                chains, stride, steps, lane, part * 64 + lane);
+                                chains, stride, steps, lane, part * 64 + lane, simple != 0);
 }
 
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).

@@ -284,7 +284,7 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
         if (waves > 0x7fffffffL) return fail(MDPE_EUNSUPPORTED, "too many wavefronts in one layer");
         hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, true>), dim3((unsigned)waves), dim3(64),
                            group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
-                           (int)group_bytes, Q);
+                           (int)group_bytes, Q, 0);
     } else {
         const size_t group_bytes =
             (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
@@ -296,11 +296,11 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
         if (wpb == 4)
             hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false>), dim3(blocks), dim3(256),
                                4 * group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
-                               (int)group_bytes, 1);
+                               (int)group_bytes, 1, P.simple ? 1 : 0);
         else
             hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false>), dim3(blocks), dim3(64), group_bytes,
                                st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
-                               (int)group_bytes, 1);
+                               (int)group_bytes, 1, P.simple ? 1 : 0);
     }
     LAUNCH_CHECK("conv_layer_kernel");
     return record(prof, 1, st, false);
@@ -534,6 +534,7 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->n_scale = (int64_t)P.scale.size();
     o->waves_per_job = P.lanes.waves_per_job;
     o->streamed = P.streamed ? 1 : 0;
+    o->simple_dealing = P.simple ? 1 : 0;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;

@@ -115,6 +115,22 @@ int stream_waves_per_job(int d, bool *paired) {
     return std::max(1, pairs / kLanes);
 }
 
+bool prefer_simple_dealing(int d, int J, int w, int schedule_steps) {
+    if (w > 2) return false;
+    // steps of dealing J*(d+1) coefficients to 64 lanes in turn: each round of
+    // 64 costs its longest coefficient; a step of it costs about 0.15 (w = 1)
+    // or 0.4-0.5 (w = 2) schedule steps (measured on p2 at d = 152; 0.5 keeps
+    // the marginal cases of the batched configuration on the schedule)
+    const long items = (long)J * (d + 1);
+    long steps = 0;
+    for (long r = 0; r < items; r += kLanes) {
+        int longest = 0;
+        for (long t = r; t < std::min(items, r + kLanes); ++t) longest = std::max(longest, (int)(t % (d + 1)) + 1);
+        steps += longest;
+    }
+    return steps * (w == 1 ? 0.15 : 0.5) < schedule_steps;
+}
+
 // Pairwise tree over `items`; pushes the jobs of round r into rounds[r].
 static int tree_rounds(std::vector<int32_t> live, std::vector<std::vector<std::array<int32_t, 2>>> &rounds) {
     int r = 0;
@@ -480,6 +496,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
             P.lanes = make_lane_schedule(d, Q > 1 ? 1 : std::max(1, std::min(kLanes, (2 * kLanes + d + 1) / (d + 2))), Q);
     } else {
         P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, w));
+        P.simple = prefer_simple_dealing(d, P.lanes.jobs_per_group, w, P.lanes.steps);
     }
     return "";
 }

@@ -70,6 +70,9 @@ struct Plan {
     // streamed operands: chosen when a job's operands would not fit in LDS, or
     // asked for; then no convolution writes its own first operand
     bool streamed = false;
+    // staged coefficients of at most two doubles: deal coefficients to lanes
+    // in turn instead of following the lane schedule (when estimated faster)
+    bool simple = false;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };
@@ -85,6 +88,9 @@ LaneSchedule make_paired_schedule(int d, int waves_per_job);
 // Streamed operands: wavefronts per job for degree d, and whether the paired
 // schedule is used (large d, where first-fit would be slow to build).
 int stream_waves_per_job(int d, bool *paired);
+// Whether a group of J jobs of degree d with w doubles per coefficient is
+// estimated faster dealt to the lanes in turn than by the lane schedule.
+bool prefer_simple_dealing(int d, int J, int w, int schedule_steps);
 int choose_jobs_per_group(int d, int w);
 
 }  // namespace mdpe

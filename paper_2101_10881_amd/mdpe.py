@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                 ("jobs_per_group", ctypes.c_int32), ("lane_steps", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64),
-                ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32)]
+                ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32),
+                ("simple_dealing", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -120,7 +120,8 @@ def test_p3_shape_bitexact(oracle_lib):
     _compare(oracle_lib, W.p3(m=3, d=8))
 
 
-@pytest.mark.parametrize("poly,m,d", [("p1", 1, 191), ("p1", 5, 95), ("p2", 2, 31), ("p3", 8, 15)])
+@pytest.mark.parametrize("poly,m,d", [("p1", 1, 191), ("p1", 5, 95), ("p2", 2, 31), ("p3", 8, 15), ("p1", 2, 64),
+                                      ("p2", 2, 152)])
 def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     # points of the precision x degree sweep: other lane schedules (two jobs
     # per workgroup at d = 95) and precisions than the benchmark configuration

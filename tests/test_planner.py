@@ -369,3 +369,11 @@ def test_streaming_chosen_by_cost():
     assert p.info["streamed"] and p.info["waves_per_job"] == 31
     # c1: thousands of jobs per layer, staged
     assert not mdpe.Plan.for_workload(W.config1(), device=-1).info["streamed"]
+
+
+@pytest.mark.parametrize("build,m,d,simple", [(W.config2, 1, 152, 1), (W.config2, 2, 152, 1), (W.config1, 2, 64, 0),
+                                              (W.config2, 4, 152, 0), (W.config1, 10, 152, 0)])
+def test_simple_dealing_choice(build, m, d, simple):
+    # coefficients of at most two doubles are dealt to lanes in turn where the
+    # planner estimates it faster than the lane schedule; never for more
+    assert mdpe.Plan.for_workload(build(m=m, d=d), device=-1).info["simple_dealing"] == simple
