@@ -1,22 +1,28 @@
 // kernels.hip -- HIP kernels for gfx950 and the C ABI of include/mdpe.h.
 //
 // Data layout in HBM (workspace A): slot-major, then coefficient, then limb:
-// A[slot][c][l], one slot = one series = (d+1)*M doubles, so the M limbs of a
-// coefficient are contiguous (80 bytes at M = 10) and a series is one
-// contiguous block.  User buffers are limb-planar [M][count][d+1]; the
-// staging and gather kernels convert.
+// A[slot][c][l], one slot = one series = (d+1)*W doubles (W = M, or 2M for
+// complex series: real limbs, then imaginary limbs), so a coefficient's
+// limbs are contiguous (80 bytes at M = 10) and a series is one contiguous
+// block.  User buffers are limb-planar [W][count][d+1]; the staging and
+// gather kernels convert.
 //
 // Kernels
 //   stage_kernel         user coeff / z -> input slots of A (+ n_k = 1 copies)
-//   conv_layer_kernel<M> one 64-lane workgroup stages J jobs' first input series
-//                        in LDS (the second is streamed from L2/HBM one step
-//                        ahead) and computes their J*(d+1) output coefficients;
+//   conv_layer_kernel    one wavefront per group of J jobs of a layer (four per
+//                        workgroup when a launch has one to three wavefronts
+//                        per SIMD) stages the jobs' first operands in LDS (both
+//                        operands for coefficients of at most two doubles; none
+//                        when operands are streamed, with Q wavefronts per
+//                        job) and computes their J*(d+1) output coefficients;
 //                        each coefficient is one lane's sequential chain
-//                        z_k = x_0 y_k, z_k += x_i y_{k-i} (i = 1..k), and the
-//                        chains are spread over the lanes by a host-made
-//                        longest-first schedule (Section 2, eq. (1); Section 5,
-//                        the convolution kernel)
-//   add_level_kernel<M>  one thread per coefficient of every pair of a level:
+//                        z_k = x_0 y_k, z_k += x_i y_{k-i} (i = 1..k), spread
+//                        over the lanes by a host-made schedule or dealt to the
+//                        lanes in turn (Section 2, eq. (1); Section 5, the
+//                        convolution kernel); complex series and the
+//                        correlations of the reverse pass run on it too
+//   scale_kernel         A[dst] := e * A[src] for general exponents (Section 3)
+//   add_level_kernel     one thread per coefficient of every pair of a level:
 //                        A[t2] := A[t2] + A[t1] (Section 5, the addition kernel)
 //   gather_kernel        output slots -> user value / gradient (zeros if absent)
 #include <hip/hip_runtime.h>

@@ -18,6 +18,12 @@
 // Addition jobs: per output list a pairwise tree, adjacent pairs with the odd
 // element carried, the later element updated (Section 5, the addition
 // recursion, read through the worked example after eq. (5)).
+//
+// General exponents (Section 3): a table of powers z_i^p := z_i^{p-1} * z_i,
+// the common factor a_k * prod z^(e-1) in front of the monomial's jobs, and a
+// scale stage (A[dst] := e * A[src]) for the partial derivatives.  Streamed
+// operands (degrees beyond one workgroup's LDS, or estimated faster): no job
+// writes its own first operand, and a job may span several wavefronts.
 #include "plan.hpp"
 
 #include <cmath>
