@@ -343,7 +343,9 @@ def load_tiles():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU design is described in DESIGN.md"}))
+        print(json.dumps({"error": f"--gpus {a.gpus}: this benchmark runs on one GPU only (the path would shard "
+                                   "by monomial ranges with one all-gather of partial series; no multi-GPU run "
+                                   "is implemented)"}))
         sys.exit(2)
     if a.workload == "c3":
         return run_c3(a)
