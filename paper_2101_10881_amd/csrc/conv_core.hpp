@@ -234,9 +234,12 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 // between one and three wavefronts per SIMD, where single-wavefront workgroups
 // can pile three onto one SIMD while another stays idle.  (A separate
 // instantiation: the 256-thread launch bound alone slows a lone wavefront.)
-// Streamed operands (XS): Q wavefronts share each group; wavefront w takes
-// group w / Q, schedule part w % Q.
-template <int M, bool CORR, bool CX = false, int WPB = 1, bool XS = false>
+// Q wavefronts share each group (Q > 1 for few jobs per layer at a large
+// degree, and for streamed operands); wavefront w takes group w / Q, schedule
+// part w % Q.
+// MQ = false: one wavefront per group (Q = 1), the mapping without a division
+// (a separate instantiation so that the common case's code is unchanged).
+template <int M, bool CORR, bool CX = false, int WPB = 1, bool XS = false, bool MQ = XS>
 __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
                                                               int njobs, int d, int J, const int *__restrict__ chains,
                                                               int stride, int steps, int group_bytes, int Q,
@@ -244,8 +247,8 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
     extern __shared__ double lds[];
     const int wave = WPB == 1 ? 0 : (int)(threadIdx.x >> 6);
     const int wv = blockIdx.x * WPB + wave;
-    const int g = XS ? wv / Q : wv;
-    const int part = XS ? wv - g * Q : 0;
+    const int g = MQ ? wv / Q : wv;
+    const int part = MQ ? wv - g * Q : 0;
     const int g0 = g * J;
     const int lane = threadIdx.x & 63;
     conv_group<M, CORR, CX, XS>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),

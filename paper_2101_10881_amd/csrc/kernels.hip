@@ -277,6 +277,8 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set = true;
     }
     if (nj == 0) return MDPE_OK;
@@ -295,17 +297,23 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
         const size_t group_bytes =
             (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
         // one wavefront per workgroup, or one per SIMD (see conv_layer_kernel)
+        const long waves = (long)groups * Q;
+        if (waves > 0x7fffffffL) return fail(MDPE_EUNSUPPORTED, "too many wavefronts in one layer");
         const int simds = simd_count(pl->device);
         const int wpb =
-            (groups > simds && groups <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
-        const int blocks = (groups + wpb - 1) / wpb;
-        if (wpb == 4)
-            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false>), dim3(blocks), dim3(256),
+            (waves > simds && waves <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
+        const long blocks = (waves + wpb - 1) / wpb;
+        if (Q > 1)
+            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>), dim3((unsigned)waves), dim3(64),
+                               group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
+                               (int)group_bytes, Q, 0);
+        else if (wpb == 4)
+            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false>), dim3((unsigned)blocks), dim3(256),
                                4 * group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
                                (int)group_bytes, 1, P.simple ? 1 : 0);
         else
-            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false>), dim3(blocks), dim3(64), group_bytes,
-                               st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
+            hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false>), dim3((unsigned)blocks), dim3(64),
+                               group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
                                (int)group_bytes, 1, P.simple ? 1 : 0);
     }
     LAUNCH_CHECK("conv_layer_kernel");

@@ -121,12 +121,9 @@ int stream_waves_per_job(int d, bool *paired) {
     return std::max(1, pairs / kLanes);
 }
 
-bool prefer_simple_dealing(int d, int J, int w, int schedule_steps) {
-    if (w > 2) return false;
+int dealt_steps(int d, int J) {
     // steps of dealing J*(d+1) coefficients to 64 lanes in turn: each round of
-    // 64 costs its longest coefficient; a step of it costs about 0.15 (w = 1)
-    // or 0.4-0.5 (w = 2) schedule steps (measured on p2 at d = 152; 0.5 keeps
-    // the marginal cases of the batched configuration on the schedule)
+    // 64 costs its longest coefficient
     const long items = (long)J * (d + 1);
     long steps = 0;
     for (long r = 0; r < items; r += kLanes) {
@@ -134,7 +131,15 @@ bool prefer_simple_dealing(int d, int J, int w, int schedule_steps) {
         for (long t = r; t < std::min(items, r + kLanes); ++t) longest = std::max(longest, (int)(t % (d + 1)) + 1);
         steps += longest;
     }
-    return steps * (w == 1 ? 0.15 : 0.5) < schedule_steps;
+    return (int)std::min(steps, (long)INT32_MAX);
+}
+
+bool prefer_simple_dealing(int d, int J, int w, int schedule_steps) {
+    // a dealt step costs about 0.15 (w = 1) or 0.4-0.5 (w = 2) schedule steps
+    // (measured on p2 at d = 152; 0.5 keeps the marginal cases of the batched
+    // configuration on the schedule)
+    if (w > 2) return false;
+    return dealt_steps(d, J) * (w == 1 ? 0.15 : 0.5) < schedule_steps;
 }
 
 // Pairwise tree over `items`; pushes the jobs of round r into rounds[r].
@@ -501,8 +506,49 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         else
             P.lanes = make_lane_schedule(d, Q > 1 ? 1 : std::max(1, std::min(kLanes, (2 * kLanes + d + 1) / (d + 2))), Q);
     } else {
-        P.lanes = make_lane_schedule(d, choose_jobs_per_group(d, w));
-        P.simple = prefer_simple_dealing(d, P.lanes.jobs_per_group, w, P.lanes.steps);
+        // jobs per wavefront J and wavefronts per job Q by the layer cost model:
+        // fewer jobs per wavefront, or several wavefronts per job, when layers
+        // have fewer wavefronts than the chip has SIMDs (deep chains such as
+        // p2), down to the longest coefficient's d+1 steps
+        // Candidates, by the layer cost model: J jobs per wavefront by the lane
+        // schedule (J0 halved down to 1), one job over Q = 2..4 wavefronts,
+        // and for coefficients of at most two doubles the same J dealt to the
+        // lanes in turn (steps weighted by their lower cost).  Fewer jobs per
+        // wavefront or several wavefronts per job pay when layers have fewer
+        // wavefronts than the chip has SIMDs (deep chains such as p2).
+        // (A candidate replaces the default only when estimated 10% faster: the
+        // model ignores staging and per-wavefront costs, e.g. c2's two jobs
+        // per wavefront measure 4% faster than one although it predicts the
+        // opposite.)  Dealt steps weigh 0.15 (m = 1) or 0.4 (m = 2): measured
+        // on p2 at d = 152.
+        const int J0 = choose_jobs_per_group(d, w);
+        double best = -1;
+        auto consider = [&](LaneSchedule &&ls, bool simple, double c) {
+            if (best < 0 || c < 0.9 * best) {
+                best = c;
+                P.lanes = std::move(ls);
+                P.simple = simple;
+            }
+        };
+        for (int J = J0;; J /= 2) {
+            LaneSchedule ls = make_lane_schedule(d, J);
+            const double c = layer_cost(P, 1, J, ls.steps, 1.0);
+            if (w <= 2) {
+                const double sc = layer_cost(P, 1, J, dealt_steps(d, J), w == 1 ? 0.15 : 0.4);
+                if (sc < c) {
+                    consider(std::move(ls), true, sc);
+                    if (J == 1) break;
+                    continue;
+                }
+            }
+            consider(std::move(ls), false, c);
+            if (J == 1) break;
+        }
+        for (int Q = 2; Q <= 4 && d + 1 >= kLanes; ++Q) {
+            LaneSchedule ls = make_lane_schedule(d, 1, Q);
+            const double c = layer_cost(P, Q, 1, ls.steps, 1.0);
+            consider(std::move(ls), false, c);
+        }
     }
     return "";
 }
