@@ -54,7 +54,7 @@ typedef struct {
     const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
                                increasing inside each monomial (Section 4) */
     uint32_t flags;         /* 0, or MDPE_KEEP_MONOMIAL_VALUES, MDPE_COMPLEX, MDPE_STREAM_OPERANDS,
-                               MDPE_STAGE_OPERANDS */
+                               MDPE_STAGE_OPERANDS, MDPE_ASAP_LAYERS */
     const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
                                (every exponent one).  Monomial k is then
                                a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
@@ -104,6 +104,14 @@ typedef struct {
  * MDPE_EUNSUPPORTED when they do not fit; excludes MDPE_STREAM_OPERANDS. */
 #define MDPE_STAGE_OPERANDS 8u
 
+/* Plan flag: keep every convolution at its earliest layer, the layering of
+ * Section 5 (p1 at four variables per monomial: 3640, 5460, 5460 and 1820
+ * jobs per layer).  Without it a plan moves jobs with slack to later layers
+ * where that fills whole rounds of the GPU's SIMDs (p1: 3072, 4096, 6144 and
+ * 3068 jobs; mdpe_plan_info.balanced_layers).  Any layering that keeps each
+ * job after the jobs it depends on gives the same output bits. */
+#define MDPE_ASAP_LAYERS 16u
+
 /* Plan summary. */
 typedef struct {
     int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
@@ -123,6 +131,8 @@ typedef struct {
     int32_t streamed;       /* 1 if the convolution operands are read from global memory */
     int32_t simple_dealing; /* 1 if coefficients (of at most two doubles) are dealt to lanes in turn
                                instead of following the lane schedule */
+    int32_t balanced_layers;/* 1 if convolutions with slack were moved to later layers (see
+                               MDPE_ASAP_LAYERS) */
 } mdpe_plan_info;
 
 /*

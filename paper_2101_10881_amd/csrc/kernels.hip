@@ -480,7 +480,8 @@ extern "C" {
 int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
-    if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS))
+    if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS |
+                                MDPE_ASAP_LAYERS))
         return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
@@ -549,6 +550,7 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->waves_per_job = P.lanes.waves_per_job;
     o->streamed = P.streamed ? 1 : 0;
     o->simple_dealing = P.simple ? 1 : 0;
+    o->balanced_layers = P.balanced ? 1 : 0;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;

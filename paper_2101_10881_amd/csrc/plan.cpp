@@ -230,15 +230,134 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
 // SIMDs) wavefront lifetimes (a SIMD's throughput hardly depends on how many
 // wavefronts share it), a streamed step costing ~1.2 staged steps (c1: 15.2
 // vs 12.9 ms at equal steps).
+constexpr long kSimds = 1024;  // MI355X: 256 CUs x 4 SIMDs
+
 static double layer_cost(const Plan &P, int waves_per_job, int jobs_per_group, int steps, double step_cost) {
-    constexpr double kSimds = 1024.0;  // MI355X: 256 CUs x 4 SIMDs
     double c = 0;
     for (int L = 1; L <= P.n_layers(); ++L) {
         const long jobs = P.conv_off[L] - P.conv_off[L - 1];
         const long waves = (jobs + jobs_per_group - 1) / jobs_per_group * waves_per_job;
-        c += std::ceil(waves / kSimds) * steps * step_cost;
+        c += std::ceil(waves / (double)kSimds) * steps * step_cost;
     }
     return c;
+}
+
+// Layer balancing.  The layering above puts every convolution at its
+// earliest layer; many jobs have slack (b_1 of a four-variable monomial is
+// needed only by b_2, c_1 by nothing but the additions), and any layering
+// that keeps each job after the jobs it depends on gives the same bits.  A
+// layer costs about ceil(wavefronts / SIMDs) rounds, so the pass moves jobs
+// with slack to later layers until each layer but the last fills whole rounds
+// of `per_round` jobs where it can (p1: 3640/5460/5460/1820 jobs, 18 rounds
+// of 1024, become 3072/4096/6144/3068, 16 rounds).  The depth stays the same.
+//
+// Dependencies come from slot accesses in the old layer order: a job depends
+// on the last writer of each slot it reads (read after write), on the last
+// writer of the slot it writes (write after write) and on every job that read
+// that slot since (write after read; a job's in-place read of its own output
+// is no dependency).  latest[j] is the last layer j can take with its
+// dependants still fitting below the depth.  Layer by layer, the ready jobs
+// (all dependencies placed earlier) are taken least slack first, then by
+// their old order: all whose latest layer this is, and beyond them as many
+// whole rounds as the ready jobs fill (or the rest of the round the
+// mandatory ones start).  Within a layer jobs keep their old relative order.
+// Returns false (P unchanged) if nothing moved.
+static bool balance_layers(Plan &P, long per_round) {
+    const int D = P.n_layers();
+    const long nj = (long)P.conv.size();
+    if (D < 2 || nj == 0 || per_round < 1) return false;
+    std::vector<int> old_layer(nj);
+    for (int L = 1; L <= D; ++L)
+        for (int64_t j = P.conv_off[L - 1]; j < P.conv_off[L]; ++j) old_layer[j] = L;
+    // edges (from, to) with from in an earlier old layer than to
+    std::vector<std::pair<int, int>> edges;
+    std::vector<int> last_writer(P.n_series, -1);
+    std::vector<int> reader_head(P.n_series, -1);  // readers since the last write, as linked lists
+    std::vector<int> reader_job, reader_next;
+    for (int L = 1; L <= D; ++L) {
+        const long lo = P.conv_off[L - 1], hi = P.conv_off[L];
+        for (long j = lo; j < hi; ++j) {
+            const auto &t = P.conv[j];
+            for (int r = 0; r < 2; ++r)
+                if (last_writer[t[r]] >= 0) edges.push_back({last_writer[t[r]], (int)j});
+            if (last_writer[t[2]] >= 0) edges.push_back({last_writer[t[2]], (int)j});
+            for (int q = reader_head[t[2]]; q >= 0; q = reader_next[q])
+                if (reader_job[q] != (int)j) edges.push_back({reader_job[q], (int)j});
+        }
+        for (long j = lo; j < hi; ++j)
+            for (int r = 0; r < 2; ++r) {
+                const int32_t s = P.conv[j][r];
+                if (r == 1 && s == P.conv[j][0]) continue;
+                reader_job.push_back((int)j);
+                reader_next.push_back(reader_head[s]);
+                reader_head[s] = (int)reader_job.size() - 1;
+            }
+        for (long j = lo; j < hi; ++j) {
+            last_writer[P.conv[j][2]] = (int)j;
+            reader_head[P.conv[j][2]] = -1;
+        }
+    }
+    // successor lists (CSR)
+    std::vector<int> sbeg(nj + 1, 0), succ(edges.size()), npred(nj, 0);
+    for (auto &e : edges) {
+        if (old_layer[e.first] >= old_layer[e.second]) return false;  // not a valid layering: leave it
+        sbeg[e.first + 1]++;
+        npred[e.second]++;
+    }
+    for (long j = 0; j < nj; ++j) sbeg[j + 1] += sbeg[j];
+    {
+        std::vector<int> fill(sbeg.begin(), sbeg.end() - 1);
+        for (auto &e : edges) succ[fill[e.first]++] = e.second;
+    }
+    std::vector<int> latest(nj, D);
+    for (long j = nj - 1; j >= 0; --j)
+        for (int q = sbeg[j]; q < sbeg[j + 1]; ++q) latest[j] = std::min(latest[j], latest[succ[q]] - 1);
+    std::vector<int> layer(nj, 0), ready, next;
+    for (long j = 0; j < nj; ++j)
+        if (npred[j] == 0) ready.push_back((int)j);
+    long placed = 0;
+    for (int L = 1; L <= D; ++L) {
+        std::sort(ready.begin(), ready.end(), [&](int a, int b) {
+            return latest[a] != latest[b] ? latest[a] < latest[b] : a < b;
+        });
+        const long nr = (long)ready.size();
+        long mand = 0;
+        while (mand < nr && latest[ready[mand]] <= L) ++mand;
+        long take = nr;
+        if (L < D) {
+            const long whole = nr / per_round * per_round;
+            take = whole >= mand ? whole : std::min(nr, (mand + per_round - 1) / per_round * per_round);
+            if (take == 0) take = nr;
+        }
+        next.clear();
+        for (long q = 0; q < nr; ++q) {
+            const int j = ready[q];
+            if (q >= take) {
+                next.push_back(j);
+                continue;
+            }
+            layer[j] = L;
+            ++placed;
+            for (int s = sbeg[j]; s < sbeg[j + 1]; ++s)
+                if (--npred[succ[s]] == 0) next.push_back(succ[s]);
+        }
+        ready.swap(next);
+    }
+    if (placed != nj || !ready.empty()) return false;
+    bool moved = false;
+    for (long j = 0; j < nj; ++j) moved |= layer[j] != old_layer[j];
+    if (!moved) return false;
+    std::vector<std::array<int32_t, 3>> conv;
+    conv.reserve(nj);
+    std::vector<int64_t> off{0};
+    for (int L = 1; L <= D; ++L) {
+        for (long j = 0; j < nj; ++j)
+            if (layer[j] == L) conv.push_back(P.conv[j]);
+        off.push_back((int64_t)conv.size());
+    }
+    P.conv.swap(conv);
+    P.conv_off.swap(off);
+    return true;
 }
 
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
@@ -259,7 +378,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
 static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
                                    const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported) {
     *unsupported = false;
-    if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands)) return "unknown flags";
+    if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers)) return "unknown flags";
     if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;
     const bool cx = (flags & kComplex) != 0;
@@ -548,6 +667,22 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
             LaneSchedule ls = make_lane_schedule(d, 1, Q);
             const double c = layer_cost(P, Q, 1, ls.steps, 1.0);
             consider(std::move(ls), false, c);
+        }
+    }
+    if (!(flags & kAsapLayers)) {
+        const int J = P.lanes.jobs_per_group, Q = P.lanes.waves_per_job;
+        const double before = layer_cost(P, Q, J, P.lanes.steps, 1.0);
+        auto conv = P.conv;
+        auto off = P.conv_off;
+        if (balance_layers(P, std::max(1L, kSimds * J / Q))) {
+            if (layer_cost(P, Q, J, P.lanes.steps, 1.0) < before) {
+                P.balanced = true;
+                auto e = check_hazards(P);
+                if (!e.empty()) return "internal planner error after layer balancing: " + e;
+            } else {
+                P.conv.swap(conv);
+                P.conv_off.swap(off);
+            }
         }
     }
     return "";

@@ -39,6 +39,7 @@ constexpr uint32_t kKeepMonomialValues = 1u;
 constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then imaginary limbs
 constexpr uint32_t kStreamOperands = 4u;   // read both convolution operands from global memory
 constexpr uint32_t kStageOperands = 8u;    // stage them in LDS (no automatic streaming)
+constexpr uint32_t kAsapLayers = 16u;      // every convolution at its earliest layer (no balancing)
 
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
@@ -73,6 +74,8 @@ struct Plan {
     // staged coefficients of at most two doubles: deal coefficients to lanes
     // in turn instead of following the lane schedule (when estimated faster)
     bool simple = false;
+    // jobs with slack moved to later layers to fill whole rounds of the SIMDs
+    bool balanced = false;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };

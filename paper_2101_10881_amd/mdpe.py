@@ -24,6 +24,7 @@ MDPE_KEEP_MONOMIAL_VALUES = 1
 MDPE_COMPLEX = 2
 MDPE_STREAM_OPERANDS = 4
 MDPE_STAGE_OPERANDS = 8
+MDPE_ASAP_LAYERS = 16
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -46,7 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64),
                 ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32),
-                ("simple_dealing", ctypes.c_int32)]
+                ("simple_dealing", ctypes.c_int32), ("balanced_layers", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -292,7 +293,7 @@ class Polynomial:
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
-                 stream_operands=None):
+                 stream_operands=None, asap_layers=False):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
@@ -300,7 +301,8 @@ class Polynomial:
         # stream_operands: None lets the plan choose, True / False forces it
         flags = ((MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0) | (MDPE_COMPLEX if complex else 0) |
                  (MDPE_STREAM_OPERANDS if stream_operands is True else 0) |
-                 (MDPE_STAGE_OPERANDS if stream_operands is False else 0))
+                 (MDPE_STAGE_OPERANDS if stream_operands is False else 0) |
+                 (MDPE_ASAP_LAYERS if asap_layers else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)
@@ -310,9 +312,9 @@ class Polynomial:
         self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
 
     @classmethod
-    def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None):
+    def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
-                   getattr(w, "exps", None), stream_operands)
+                   getattr(w, "exps", None), stream_operands, asap_layers)
 
     def new_workspace(self):
         import torch

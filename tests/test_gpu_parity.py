@@ -129,6 +129,28 @@ def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     _compare(oracle_lib, build(m=m, d=d))
 
 
+@pytest.mark.parametrize("case", ["p1_m2", "p1_exponents_m2", "p1_m3_d32", "p1_keep_m1"])
+def test_balanced_layers_bitexact(oracle_lib, case):
+    # p1's shape at these degrees plans with convolutions moved to later
+    # layers to fill whole rounds of the SIMDs: the oracle's bits, and the
+    # earliest-layer plan's bits
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = {"p1_m2": lambda: W.config1(m=2), "p1_exponents_m2": lambda: W.with_exponents(W.config1(m=2), 3, seed=5),
+         "p1_m3_d32": lambda: W.config1(m=3, d=32), "p1_keep_m1": lambda: W.config1(m=1)}[case]()
+    keep = case.startswith("p1_keep")
+    dev = torch.device("cuda", 0)
+    bal = mdpe.Polynomial.for_workload(w, dev, keep_monomials=keep)
+    asap = mdpe.Polynomial.for_workload(w, dev, keep_monomials=keep, asap_layers=True)
+    assert bal.plan.info["balanced_layers"] == 1 and asap.plan.info["balanced_layers"] == 0
+    _say(f"balanced layers {case}: {bal.plan.layer_sizes()[0]}")
+    want_v, want_g = oracle_lib.eval_workload(w)
+    for P in (bal, asap):
+        got_v, got_g = run_gpu(w, poly=P)
+        assert_bitexact(got_v, want_v, f"{case} value")
+        assert_bitexact(got_g, want_g, f"{case} gradient")
+
+
 @pytest.mark.parametrize("m,d,cx", [(10, 1637, False), (10, 818, True), (1, 8191, False), (2, 4095, False),
                                      (4, 2000, False)])
 def test_maximum_degrees_bitexact(oracle_lib, m, d, cx):
