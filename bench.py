@@ -282,6 +282,39 @@ def measure_streamed(steps, warmup):
     return out
 
 
+def measure_layering(steps, warmup):
+    """c1 with the earliest-layer layering of Section 5 (MDPE_ASAP_LAYERS:
+    3640/5460/5460/1820 jobs, 18 rounds of the 1024 SIMDs) beside the default
+    balanced one (3072/4096/6144/3068, 16 rounds); outputs compared bitwise."""
+    import torch
+
+    from paper_2101_10881_amd import mdpe
+    from paper_2101_10881_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    w = W.config1()
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    out, bits = {}, []
+    for key, asap in (("earliest", True), ("balanced", False)):
+        P = mdpe.Polynomial.for_workload(w, dev, asap_layers=asap)
+        v, g = P.eval_and_diff(coeff, z)
+        for _ in range(warmup):
+            P.eval_and_diff(coeff, z, v, g)
+        torch.cuda.synchronize()
+        prof = mdpe.Profiler()
+        for _ in range(steps):
+            P.eval_and_diff(coeff, z, v, g, profiler=prof)
+        t = prof.read()
+        bits.append((v.view(torch.int64).clone(), g.view(torch.int64).clone()))
+        out[key] = {"conv_launches": [int(x) for x in P.plan.layer_sizes()[0]],
+                    "cnv_ms": round(t["cnv_ms"] / steps, 4)}
+        del P, v, g
+    out["workload"] = w.name
+    out["bitexact"] = bool(torch.equal(bits[0][0], bits[1][0]) and torch.equal(bits[0][1], bits[1][1]))
+    return out
+
+
 def sweep_workload(poly, m, d, cx=False, emax=1):
     from paper_2101_10881_amd import workloads as W
     w = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
@@ -453,6 +486,7 @@ def main():
         out["autograd_c4"] = measure_c4(10, 2)
         out["complex_p1"] = measure_complex(5, 1)
         out["streamed_operands"] = measure_streamed(3, 1)
+        out["layer_balancing"] = measure_layering(5, 1)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
