@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -83,24 +84,29 @@ def cpu_baseline(target_s):
     cores = len(os.sched_getaffinity(0))
     full = W.config1()
 
-    def sample(K):
+    def sample(K, threads):
         sup = full.supports()[:K]
         w = W.make(f"p1_first{K}", 10, 152, 16, sup, seed=1)
         t0 = time.perf_counter()
-        O.eval_workload(w, nthreads=cores)
+        O.eval_workload(w, nthreads=threads)
         dt = time.perf_counter() - t0
         i = mdpe.Plan.for_workload(w, device=-1).info
         work = i["n_conv"] * flops.conv_flops(10, 152) + i["n_add"] * flops.add_flops(10, 152)
         return dt, work
 
     K0 = max(cores, 8)
-    dt0, _ = sample(K0)
+    dt0, _ = sample(K0, cores)
     K = int(min(1820, max(K0, K0 * target_s / max(dt0, 1e-3))))
-    dt, work = sample(K)
+    dt, work = sample(K, cores)
+    # one thread, on a few monomials (a couple of seconds)
+    K1 = 48
+    dt1, work1 = sample(K1, 1)
     return {"value": work / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"first {K} of the 1820 monomials of p1, m=10, d=152, seed 1 ({dt:.1f} s wall, "
                       f"{cores} OpenMP threads, same flop accounting as value)",
-            "seconds": dt}
+            "seconds": dt,
+            "single_thread": {"value": round(work1 / dt1 / 1e9, 3), "unit": "GFLOP/s",
+                              "sample": f"first {K1} monomials, 1 thread ({dt1:.1f} s wall)"}}
 
 
 def measure_c3(instances, steps, warmup):
@@ -315,6 +321,34 @@ def measure_layering(steps, warmup):
     return out
 
 
+def measure_seeds(P, steps):
+    """c1's step time for the input seeds 2..10 with the same plan (p1's
+    supports do not depend on the seed; the series values do), the spread the
+    paper reports over seeds (Table 8)."""
+    import torch
+
+    from paper_2101_10881_amd import workloads as W
+
+    dev = P.workspace.device
+    ms = {}
+    for seed in range(2, 11):
+        w = W.config1(seed=seed)
+        coeff = torch.from_numpy(w.coeff).to(dev)
+        z = torch.from_numpy(w.z).to(dev)
+        v, g = P.eval_and_diff(coeff, z)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            P.eval_and_diff(coeff, z, v, g)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[seed] = round(e0.elapsed_time(e1) / steps, 4)
+    vals = sorted(ms.values())
+    return {"workload": "c1_p1_10d_d152", "steps_per_seed": steps, "ms_per_step": ms,
+            "median": vals[len(vals) // 2], "min": vals[0], "max": vals[-1]}
+
+
 def sweep_workload(poly, m, d, cx=False, emax=1):
     from paper_2101_10881_amd import workloads as W
     w = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
@@ -413,16 +447,18 @@ def main():
     torch.cuda.synchronize()
 
     prof = mdpe.Profiler()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps: the whole region and each step's time
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(a.steps):
+    marks[0].record(stream)
+    for k in range(a.steps):
         P.eval_and_diff(coeff, z, value, grad, profiler=prof)
-    stop.record(stream)
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(stop)
+    total_ms = marks[0].elapsed_time(marks[-1])
+    per_step = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(a.steps))
     kt = prof.read()
 
     m, d = w.m, w.d
@@ -446,6 +482,8 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "step_ms": {"median": round(statistics.median(per_step), 4), "min": round(per_step[0], 4),
+                    "max": round(per_step[-1], 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -487,6 +525,7 @@ def main():
         out["complex_p1"] = measure_complex(5, 1)
         out["streamed_operands"] = measure_streamed(3, 1)
         out["layer_balancing"] = measure_layering(5, 1)
+        out["seed_spread"] = measure_seeds(P, 3)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

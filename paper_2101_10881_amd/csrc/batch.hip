@@ -217,11 +217,13 @@ void free_batch(mdpe_batch *b) {
 // workgroups), resolved once, outside any stream capture.
 template <int M1, int M2>
 int prepare_batch(mdpe_batch *b) {
-    static bool attr = false;
-    if (b->lds > 65536 && !attr) {
+    // the LDS limit is a per-device function attribute: raise it once per device
+    static std::atomic<bool> attr[kMaxDevices];
+    const int dv = b->device >= 0 && b->device < kMaxDevices ? b->device : 0;
+    if (b->lds > 65536 && !attr[dv].load()) {
         BHIP(hipFuncSetAttribute((const void *)mdpe::batch_kernel<M1, M2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)mdpe::kMaxLdsBytes));
-        attr = true;
+        attr[dv].store(true);
     }
     if (b->grid == 0) {
         int per_cu = 0, cus = 0;
@@ -348,8 +350,7 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         const mdpe::LaneSchedule &S = scheds[sched_index[key]];
         const int G = t.groups_per_task > 0 ? t.groups_per_task : std::max(1, (256 + S.steps - 1) / S.steps);
         const long items_per_task = t.add_items_per_task > 0 ? t.add_items_per_task : 4096;
-        lds = std::max(lds, (size_t)mdpe::conv_lds_jobs_offset((long)J * (P.d + 1) * mdpe::lds_doubles_per_coef(P.m)) +
-                                (size_t)J * 16);
+        lds = std::max(lds, (size_t)mdpe::group_lds_bytes(P.d + 1, mdpe::lds_doubles_per_coef(P.m), J));
         if (lds > (size_t)mdpe::kMaxLdsBytes)
             return bfail(MDPE_EUNSUPPORTED, "a tile's jobs_per_group needs more LDS than one workgroup has");
         mdpe::BatchInst &I = B->insts[p];

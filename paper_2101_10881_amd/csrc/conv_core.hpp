@@ -10,12 +10,16 @@
 
 namespace mdpe {
 
-// One lane's position in its list of output coefficients.
+// One lane's position in its list of output coefficients, with the addresses
+// of the operand coefficients of its current term and of its output.
 struct ChainState {
     int c;      // index in the lane's chain list
     int code;   // (job << 16) | k, or -1 when the lane is done
+    int next;   // the code after it (-1 past the terminator)
     int j, k, i;
     bool live;  // computes a real coefficient (job j exists in this group)
+    const double *x, *y;  // first and second operand coefficient of term i
+    double *out;          // the output coefficient
 };
 
 __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
@@ -31,10 +35,21 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
     st.i = 0;
 }
 
+// A job's three series as offsets (in doubles) into A: first operand, second
+// operand, output.  Kept in LDS, so that a lane starting a chain finds its
+// operands' addresses with one LDS read and an add.
+struct JobOffsets {
+    long x, y, z, unused;
+};
+
 // LDS layout of one wavefront's group: X[J][d+1][W] doubles (the first
 // operands), Y[J][d+1][W] (the second operands, only when
-// stages_second_operand(W)), then the J job descriptors (16-byte aligned).
+// stages_second_operand(W)), then the J JobOffsets (16-byte aligned).
+// `doubles_per_coef` is lds_doubles_per_coef(W), or 0 for streamed operands.
 __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
+__host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, int J) {
+    return conv_lds_jobs_offset((long)J * d1 * doubles_per_coef) + (long)J * (long)sizeof(JobOffsets);
+}
 
 // CORR = false: convolution z_k = sum_{i=0..k} x_i y_{k-i} (eq. (1)).
 // CORR = true:  correlation z_s = sum_{j=0..d-s} x_{s+j} y_j (the reverse pass);
@@ -43,8 +58,8 @@ __host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xd
 // CX = true: complex series, W = 2M doubles per coefficient (cmd_mul, cmd_add).
 // One 64-lane wavefront computes jn <= J jobs jobs[0..jn) (the output
 // coefficients of each spread over the lanes by the schedule `chains`).
-// lds must hold conv_lds_jobs_offset(J*(d+1)*lds_doubles_per_coef(W)) + J*16
-// bytes.  Ends with the wavefront's stores issued (not necessarily complete).
+// lds must hold group_lds_bytes(d+1, lds_doubles_per_coef(W), J) bytes (0
+// doubles per coefficient when streamed).  Ends with the wavefront's stores issued (not necessarily complete).
 // XS = true (streamed operands, for degrees whose operands do not fit in LDS):
 // both operands are read from global memory and only the job descriptors are
 // in LDS; the planner then guarantees that no job writes its first operand.
@@ -61,7 +76,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     const long S = (long)(d + 1) * W;
     double *X = lds;
     double *Y = lds + J * S;  // used when YL
-    int4 *jd = (int4 *)((char *)lds + (XS ? 0 : conv_lds_jobs_offset(J * (YL ? 2 : 1) * S)));
+    JobOffsets *jd = (JobOffsets *)((char *)lds + (XS ? 0 : conv_lds_jobs_offset(J * (YL ? 2 : 1) * S)));
     // Stage the first operand of every job in LDS: it is read by all lanes and
     // may be the job's own output (the in-place b := b * a of Section 3).  The
     // second operand is never the output (the planner checks) and is streamed
@@ -79,7 +94,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
             const double *ys = A + (long)t.y * S;
             for (long q = lane; q < S; q += 64) Y[j * S + q] = ys[q];
         }
-        if (lane == 0) jd[j] = t;
+        if (lane == 0) jd[j] = JobOffsets{(long)t.x * S, (long)t.y * S, (long)t.z * S, 0};
     }
     __syncthreads();
     if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barrier)
@@ -98,7 +113,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
                 const int k = t - j * d1;
                 const double *x = X + (long)j * S;
                 const double *y = Y + (long)j * S;
-                double *out = A + (long)jd[j].z * S + (long)(CORR ? d - k : k) * W;
+                double *out = A + jd[j].z + (long)(CORR ? d - k : k) * W;
                 // CORR: z_s = sum_{i=0..d-s} x_{s+i} y_i with s = d - k (k+1 terms)
                 const int x0 = CORR ? d - k : 0;
                 double acc[W], pr[W], xa[W], ya[W];
@@ -125,88 +140,79 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     }
 
     const int *my = chains + (long)row * stride;
-    // Next position in the lane's chain list (reads the -1 terminator at most).
-    auto advance = [&](const ChainState &cur, ChainState &nxt, int4 &nj) {
-        nxt = cur;
-        if (cur.i == cur.k) {
-            if (cur.code >= 0) nxt.code = my[++nxt.c];
-            chain_decode(nxt, jn);
-            if (nxt.live) nj = jd[nxt.j];
-        } else {
-            nxt.i = cur.i + 1;
-        }
-    };
     auto xidx = [&](int k, int i) { return CORR ? d - k + i : i; };
     auto yidx = [&](int k, int i) { return CORR ? i : k - i; };
+    // Addresses of a chain's first term and of its output coefficient: LDS,
+    // or global memory when streamed.  A lane with no chain (code -1, or a job
+    // past the group's last) gets those of job 0's coefficient, so every lane
+    // may load at every step and no load needs a guard; such lanes never store.
+    auto start = [&](ChainState &t) {
+        const int j = t.live ? t.j : 0;
+        const JobOffsets &jb = jd[j];
+        t.x = XS ? A + jb.x + (long)xidx(t.k, 0) * W : X + j * S + xidx(t.k, 0) * W;
+        t.y = YL ? Y + j * S + yidx(t.k, 0) * W : A + jb.y + (long)yidx(t.k, 0) * W;
+        t.out = A + jb.z + (long)(CORR ? d - t.k : t.k) * W;
+    };
+    // Next position in the lane's chain list.  The code after the current
+    // chain's is loaded at every step, outside the branch, so that a chain's
+    // start never waits for memory: at the -1 terminator the index stays on
+    // it, so the list is never read past.
+    auto advance = [&](const ChainState &cur, ChainState &nxt) {
+        nxt = cur;
+        if (cur.i == cur.k) {
+            nxt.code = cur.next;
+            if (cur.code >= 0) ++nxt.c;
+            chain_decode(nxt, jn);
+            start(nxt);
+        } else {
+            nxt.i = cur.i + 1;
+            nxt.x += W;
+            nxt.y += CORR ? W : -W;
+        }
+        nxt.next = my[nxt.c + (nxt.code >= 0 ? 1 : 0)];
+    };
 
     // Software pipeline over the lane's steps: iteration s accumulates the
     // product of step s while it computes the product of step s+1 (the two are
-    // independent, and sit in one basic block so the scheduler can interleave
-    // them) and loads the second operand of step s+2.
+    // independent) and loads the second operand of step s+2 (and, streamed,
+    // the first).
     ChainState st;
     st.c = 0;
     st.code = my[0];
+    st.next = my[st.code >= 0 ? 1 : 0];
     chain_decode(st, jn);
-    int4 job = jd[st.live ? st.j : 0];
-    // the first operand of a position: LDS, or global memory when streamed
-    auto xaddr = [&](const ChainState &t, const int4 &jb) -> const double * {
-        return XS ? A + (long)jb.x * S + (long)xidx(t.k, t.i) * W : X + t.j * S + xidx(t.k, t.i) * W;
-    };
+    start(st);
     double p[W];
     {
-        const double *xp = xaddr(st, job);
-        const double *yp = YL ? Y + st.j * S + yidx(st.k, 0) * W : A + (long)job.y * S + (long)yidx(st.k, 0) * W;
         double x0[W], y0[W];
 #pragma unroll
         for (int l = 0; l < W; ++l) {
-            x0[l] = XS ? (st.live ? xp[l] : 0.0) : xp[l];
-            y0[l] = st.live ? yp[l] : 0.0;
+            x0[l] = st.x[l];
+            y0[l] = st.y[l];
         }
         coef_mul<M, CX>(x0, y0, p);
     }
     ChainState nx;
-    int4 njob = job;
-    advance(st, nx, njob);
+    advance(st, nx);
     double yn[W], xn[W];
-    {
-        const double *yp = YL ? Y + nx.j * S + yidx(nx.k, nx.i) * W : A + (long)njob.y * S + (long)yidx(nx.k, nx.i) * W;
-        const bool fetch = nx.live && 1 < steps;
 #pragma unroll
-        for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
-        if (XS) {  // streamed: x is read two steps ahead too
-            const double *xp = xaddr(nx, njob);
-#pragma unroll
-            for (int l = 0; l < W; ++l) xn[l] = fetch ? xp[l] : 0.0;
-        }
+    for (int l = 0; l < W; ++l) {
+        yn[l] = nx.y[l];
+        if (XS) xn[l] = nx.x[l];
     }
     double acc[W];
 #pragma unroll
     for (int l = 0; l < W; ++l) acc[l] = 0.0;
     for (int s = 0; s < steps; ++s) {
         ChainState n2;
-        int4 n2job = njob;
-        advance(nx, n2, n2job);
+        advance(nx, n2);
         double x1[W], y1[W];
 #pragma unroll
-        for (int l = 0; l < W; ++l) y1[l] = yn[l];
-        {
-            const bool fetch = n2.live && s + 2 < steps;
-            if (XS) {
-                const double *xp = xaddr(n2, n2job);
-#pragma unroll
-                for (int l = 0; l < W; ++l) {
-                    x1[l] = xn[l];
-                    xn[l] = fetch ? xp[l] : 0.0;
-                }
-            } else {
-                const double *xp = xaddr(nx, njob);
-#pragma unroll
-                for (int l = 0; l < W; ++l) x1[l] = xp[l];
-            }
-            const double *yp = YL ? Y + n2.j * S + yidx(n2.k, n2.i) * W
-                                  : A + (long)n2job.y * S + (long)yidx(n2.k, n2.i) * W;
-#pragma unroll
-            for (int l = 0; l < W; ++l) yn[l] = fetch ? yp[l] : 0.0;
+        for (int l = 0; l < W; ++l) {
+            y1[l] = yn[l];
+            x1[l] = XS ? xn[l] : nx.x[l];
+            yn[l] = n2.y[l];
+            if (XS) xn[l] = n2.x[l];
         }
         double pn[W], r[W];
         coef_mul<M, CX>(x1, y1, pn);   // step s+1 (unused past the lane's last step)
@@ -215,14 +221,11 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
 #pragma unroll
         for (int l = 0; l < W; ++l) acc[l] = first ? p[l] : r[l];
         if (st.i == st.k && st.live) {
-            double *out = A + (long)job.z * S + (long)(CORR ? d - st.k : st.k) * W;
 #pragma unroll
-            for (int l = 0; l < W; ++l) out[l] = acc[l];
+            for (int l = 0; l < W; ++l) st.out[l] = acc[l];
         }
         st = nx;
-        job = njob;
         nx = n2;
-        njob = n2job;
 #pragma unroll
         for (int l = 0; l < W; ++l) p[l] = pn[l];
     }

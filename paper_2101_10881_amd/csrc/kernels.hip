@@ -165,8 +165,8 @@ namespace {
 
 using mdpe::g_err;
 
-size_t conv_lds_bytes(int d, int m, int J) {
-    return (size_t)mdpe::conv_lds_jobs_offset((long)J * (d + 1) * m) + (size_t)J * sizeof(int4);
+size_t conv_lds_bytes(int d, int doubles_per_coef, int J) {
+    return (size_t)mdpe::group_lds_bytes(d + 1, doubles_per_coef, J);
 }
 
 int fail(int code, const std::string &msg) {
@@ -255,8 +255,8 @@ int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
     } while (0)
 
 int simd_count(int device) {
-    static int cached[64] = {0};
-    if (device < 0 || device >= 64) return 1024;
+    static std::atomic<int> cached[kMaxDevices];
+    if (device < 0 || device >= kMaxDevices) return 1024;
     if (!cached[device]) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
@@ -271,15 +271,17 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
     const mdpe::Plan &P = pl->P;
     const int J = P.lanes.jobs_per_group;
     const int Q = P.lanes.waves_per_job;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // the LDS limit is a per-device function attribute: raise it once per device
+    static std::atomic<bool> attr_set[kMaxDevices];
+    const int dv = pl->device >= 0 && pl->device < kMaxDevices ? pl->device : 0;
+    if (!attr_set[dv].load()) {
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
-        attr_set = true;
+        attr_set[dv].store(true);
     }
     if (nj == 0) return MDPE_OK;
     const int groups = (nj + J - 1) / J;

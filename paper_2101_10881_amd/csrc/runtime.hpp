@@ -5,9 +5,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 
 #include "plan.hpp"
+
+// devices whose per-device state (kernel attributes, SIMD counts) is cached
+constexpr int kMaxDevices = 64;
 
 struct mdpe_plan {
     mdpe::Plan P;
