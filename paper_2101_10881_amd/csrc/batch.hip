@@ -97,8 +97,11 @@ __global__ __launch_bounds__(64) void batch_reset_kernel(int *ctl, int n) {
 // ctl[q] = next task of queue q, ctl[kQueues] = error flag,
 // ctl[kQueues + 1 + p] = completion counter of instance p.
 // qinfo[q] = first task of queue q, qinfo[kQueues + q] = its task count.
+// Up to quad double the kernel asks for six resident wavefronts per SIMD
+// (at most 80 VGPRs, no spills), the occupancy its register use allowed
+// before the convolution loop kept operand addresses per lane.
 template <int M1, int M2>
-__global__ __launch_bounds__(64) void batch_kernel(const BatchTask *__restrict__ tasks, const int *__restrict__ qinfo,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(M2 <= 4 ? 6 : 1))) void batch_kernel(const BatchTask *__restrict__ tasks, const int *__restrict__ qinfo,
                                                    const BatchInst *__restrict__ insts, int *ctl) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;

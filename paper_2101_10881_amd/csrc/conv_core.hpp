@@ -13,9 +13,9 @@ namespace mdpe {
 // One lane's position in its list of output coefficients, with the addresses
 // of the operand coefficients of its current term and of its output.
 struct ChainState {
-    int c;      // index in the lane's chain list
+    const int *cp;  // the lane's chain list entry after the current one (stays on the terminator)
     int code;   // (job << 16) | k, or -1 when the lane is done
-    int next;   // the code after it (-1 past the terminator)
+    int next;   // *cp: the code after it
     int j, k, i;
     bool live;  // computes a real coefficient (job j exists in this group)
     const double *x, *y;  // first and second operand coefficient of term i
@@ -155,13 +155,13 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     };
     // Next position in the lane's chain list.  The code after the current
     // chain's is loaded at every step, outside the branch, so that a chain's
-    // start never waits for memory: at the -1 terminator the index stays on
-    // it, so the list is never read past.
+    // start never waits for memory; the list pointer stops on the -1
+    // terminator, so the list is never read past.
     auto advance = [&](const ChainState &cur, ChainState &nxt) {
         nxt = cur;
         if (cur.i == cur.k) {
             nxt.code = cur.next;
-            if (cur.code >= 0) ++nxt.c;
+            if (nxt.code >= 0) ++nxt.cp;
             chain_decode(nxt, jn);
             start(nxt);
         } else {
@@ -169,7 +169,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
             nxt.x += W;
             nxt.y += CORR ? W : -W;
         }
-        nxt.next = my[nxt.c + (nxt.code >= 0 ? 1 : 0)];
+        nxt.next = *nxt.cp;
     };
 
     // Software pipeline over the lane's steps: iteration s accumulates the
@@ -177,9 +177,9 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     // independent) and loads the second operand of step s+2 (and, streamed,
     // the first).
     ChainState st;
-    st.c = 0;
     st.code = my[0];
-    st.next = my[st.code >= 0 ? 1 : 0];
+    st.cp = my + (st.code >= 0 ? 1 : 0);
+    st.next = *st.cp;
     chain_decode(st, jn);
     start(st);
     double p[W];
