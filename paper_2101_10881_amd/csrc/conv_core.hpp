@@ -67,7 +67,12 @@ __host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, i
 // the wavefronts sharing a job).  `simple` (coefficients of at most two
 // doubles, staged operands): deal the coefficients to the lanes in turn
 // instead of following the schedule (see below).
-template <int M, bool CORR, bool CX = false, bool XS = false>
+// CODE_AHEAD: load the code of a lane's next chain at every step, outside
+// the chain-start branch, instead of inside it.  Measured on lone wavefronts
+// (p2's layers): 15-18% faster for jobs spread over several wavefronts
+// (p2 10d, d = 152), 15% slower for groups of several jobs per wavefront
+// (p2 10d, d = 63; c4), equal on c1; the kernel chooses per instantiation.
+template <int M, bool CORR, bool CX = false, bool XS = false, bool CODE_AHEAD = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
                                            int steps, int lane, int row, bool simple = false) {
@@ -154,14 +159,15 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
         t.out = A + jb.z + (long)(CORR ? d - t.k : t.k) * W;
     };
     // Next position in the lane's chain list.  The code after the current
-    // chain's is loaded at every step, outside the branch, so that a chain's
-    // start never waits for memory; the list pointer stops on the -1
+    // chain's is loaded a chain ahead of its use (at a chain's start, or at
+    // every step with CODE_AHEAD); the list pointer stops on the -1
     // terminator, so the list is never read past.
     auto advance = [&](const ChainState &cur, ChainState &nxt) {
         nxt = cur;
         if (cur.i == cur.k) {
             nxt.code = cur.next;
             if (nxt.code >= 0) ++nxt.cp;
+            if (!CODE_AHEAD) nxt.next = *nxt.cp;
             chain_decode(nxt, jn);
             start(nxt);
         } else {
@@ -169,7 +175,7 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
             nxt.x += W;
             nxt.y += CORR ? W : -W;
         }
-        nxt.next = *nxt.cp;
+        if (CODE_AHEAD) nxt.next = *nxt.cp;
     };
 
     // Software pipeline over the lane's steps: iteration s accumulates the
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
     const int part = MQ ? wv - g * Q : 0;
     const int g0 = g * J;
     const int lane = threadIdx.x & 63;
-    conv_group<M, CORR, CX, XS>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
+    conv_group<M, CORR, CX, XS, MQ>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
                                 chains, stride, steps, lane, part * 64 + lane, simple != 0);
 }
 
