@@ -64,7 +64,7 @@ __host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, i
 // both operands are read from global memory and only the job descriptors are
 // in LDS; the planner then guarantees that no job writes its first operand.
 // `row` selects the lane's row of the schedule (q*64 + lane for the q-th of
-// the wavefronts sharing a job).  `simple` (coefficients of at most two
+// the nrows / 64 wavefronts sharing a job).  `simple` (coefficients of at most two
 // doubles, staged operands): deal the coefficients to the lanes in turn
 // instead of following the schedule (see below).
 // CODE_AHEAD: load the code of a lane's next chain at every step, outside
@@ -75,7 +75,7 @@ __host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, i
 template <int M, bool CORR, bool CX = false, bool XS = false, bool CODE_AHEAD = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
-                                           int steps, int lane, int row, bool simple = false) {
+                                           int steps, int lane, int row, bool simple = false, int nrows = kLanes) {
     constexpr int W = kCoef<M, CX>;
     constexpr bool YL = !XS && stages_second_operand(W);
     const long S = (long)(d + 1) * W;
@@ -111,9 +111,11 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
             // Instead the group's (job, coefficient) items are dealt to the
             // lanes in turn and each lane sums its coefficient's terms in the
             // specified order from the staged operands: more lane-steps, far
-            // fewer instructions per step (the planner weighs the two).
+            // fewer instructions per step (the planner weighs the two).  With
+            // several wavefronts per group, row r of the nrows = 64Q takes
+            // items r, r + 64Q, ...
             const int d1 = d + 1;
-            for (int t = lane; t < jn * d1; t += 64) {
+            for (int t = row; t < jn * d1; t += nrows) {
                 const int j = t / d1;
                 const int k = t - j * d1;
                 const double *x = X + (long)j * S;
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
     const int g0 = g * J;
     const int lane = threadIdx.x & 63;
     conv_group<M, CORR, CX, XS, MQ>(A, jobs + g0, min(J, njobs - g0), J, d, (double *)((char *)lds + wave * group_bytes),
-                                chains, stride, steps, lane, part * 64 + lane, simple != 0);
+                                    chains, stride, steps, lane, part * 64 + lane, simple != 0, (MQ ? Q : 1) * 64);
 }
 
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).

@@ -308,7 +308,7 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
         if (Q > 1)
             hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>), dim3((unsigned)waves), dim3(64),
                                group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
-                               (int)group_bytes, Q, 0);
+                               (int)group_bytes, Q, P.simple ? 1 : 0);
         else if (wpb == 4)
             hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false>), dim3((unsigned)blocks), dim3(256),
                                4 * group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,

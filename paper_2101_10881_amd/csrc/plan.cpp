@@ -121,17 +121,22 @@ int stream_waves_per_job(int d, bool *paired) {
     return std::max(1, pairs / kLanes);
 }
 
-int dealt_steps(int d, int J) {
-    // steps of dealing J*(d+1) coefficients to 64 lanes in turn: each round of
-    // 64 costs its longest coefficient
+int dealt_steps(int d, int J, int Q) {
+    // steps of dealing J*(d+1) coefficients to the 64*Q lanes of Q wavefronts
+    // in turn (item t to lane t mod 64Q): each round of 64 items of a
+    // wavefront costs its longest coefficient; the slowest wavefront counts
     const long items = (long)J * (d + 1);
-    long steps = 0;
-    for (long r = 0; r < items; r += kLanes) {
-        int longest = 0;
-        for (long t = r; t < std::min(items, r + kLanes); ++t) longest = std::max(longest, (int)(t % (d + 1)) + 1);
-        steps += longest;
+    long worst = 0;
+    for (int q = 0; q < Q; ++q) {
+        long steps = 0;
+        for (long r = (long)q * kLanes; r < items; r += (long)kLanes * Q) {
+            int longest = 0;
+            for (long t = r; t < std::min(items, r + kLanes); ++t) longest = std::max(longest, (int)(t % (d + 1)) + 1);
+            steps += longest;
+        }
+        worst = std::max(worst, steps);
     }
-    return (int)std::min(steps, (long)INT32_MAX);
+    return (int)std::min(worst, (long)INT32_MAX);
 }
 
 bool prefer_simple_dealing(int d, int J, int w, int schedule_steps) {
@@ -668,6 +673,10 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
             const double c = layer_cost(P, Q, 1, ls.steps, 1.0);
             consider(std::move(ls), false, c);
         }
+        // one job's coefficients dealt over Q wavefronts (deep chains of small
+        // layers, such as p2, at one or two doubles per coefficient)
+        for (int Q = 2; Q <= 4 && w <= 2 && d + 1 > (Q - 1) * kLanes; ++Q)
+            consider(make_lane_schedule(d, 1, Q), true, layer_cost(P, Q, 1, dealt_steps(d, 1, Q), w == 1 ? 0.15 : 0.4));
     }
     if (!(flags & kAsapLayers)) {
         const int J = P.lanes.jobs_per_group, Q = P.lanes.waves_per_job;

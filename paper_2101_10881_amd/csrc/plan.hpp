@@ -94,8 +94,9 @@ int stream_waves_per_job(int d, bool *paired);
 // Whether a group of J jobs of degree d with w doubles per coefficient is
 // estimated faster dealt to the lanes in turn than by the lane schedule.
 bool prefer_simple_dealing(int d, int J, int w, int schedule_steps);
-// Steps of a group of J jobs of degree d dealt to the lanes in turn.
-int dealt_steps(int d, int J);
+// Steps of a group of J jobs of degree d dealt to the lanes of Q wavefronts in
+// turn (the slowest wavefront's).
+int dealt_steps(int d, int J, int Q = 1);
 int choose_jobs_per_group(int d, int w);
 
 }  // namespace mdpe

@@ -55,6 +55,19 @@ def test_adjoint_edge_cases(oracle_lib):
              W.upstream_adjoint(10, 12))
 
 
+@pytest.mark.parametrize("m", [1, 2])
+def test_adjoint_dealt_over_wavefronts(oracle_lib, m):
+    # few jobs per layer at d = 152 and one or two doubles per coefficient: the
+    # plan deals each job's coefficients over several wavefronts, the reverse
+    # layer's correlations too
+    from paper_2101_10881_amd import mdpe
+    rng = np.random.default_rng(870 + m)
+    w = W.random_poly(f"adj_dealt_m{m}", m, 152, 8, 12, rng.integers(2, 6, size=12), 5)
+    i = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_KEEP_MONOMIAL_VALUES).info
+    assert i["simple_dealing"] == 1 and i["waves_per_job"] >= 2
+    _compare(oracle_lib, w, W.md_series(rng, 1, m, 152)[:, 0, :])
+
+
 def test_config4_adjoint_bitexact(oracle_lib):
     w = W.config4()
     _compare(oracle_lib, w, W.upstream_adjoint(w.m, w.d, seed=1))

@@ -381,10 +381,13 @@ def test_simple_dealing_choice(build, m, d, simple):
 
 
 @pytest.mark.parametrize("build,m,d,J,Q", [(W.config1, 10, 152, 1, 1), (W.config2, 4, 64, 2, 1),
-                                           (W.config2, 10, 152, 1, 2), (W.config2, 4, 152, 1, 2)])
+                                           (W.config2, 10, 152, 1, 2), (W.config2, 4, 152, 1, 2),
+                                           (W.config2, 1, 152, 1, 2), (W.config2, 2, 95, 1, 2),
+                                           (W.config1, 2, 152, 1, 1)])
 def test_jobs_and_wavefronts_per_group(build, m, d, J, Q):
     # layers with fewer wavefronts than SIMDs (p2's 378 jobs) spread a job over
-    # two wavefronts, down to the longest coefficient's d+1 steps
+    # two wavefronts, down to the longest coefficient's d+1 steps; at one or two
+    # doubles per coefficient by dealing the coefficients over them
     i = mdpe.Plan.for_workload(build(m=m, d=d), device=-1).info
     assert (i["jobs_per_group"], i["waves_per_job"]) == (J, Q)
     if Q > 1:
