@@ -138,3 +138,25 @@ def test_wavefronts_running_many_tasks(grid):
     got, _ = _batched(ws, tiles=small, grid=grid, graph=True, replays=2)
     _check(got[0], want, f"grid {grid}")
     _check(got[1], want, f"grid {grid} replay")
+
+
+def test_config3_full_size(oracle_lib):
+    # the batched configuration as the benchmark times it: 512 instances,
+    # autotuned tiles, one graph launch; every instance bitwise equal to its
+    # plain evaluation, and one instance of each (m, d) bucket to the oracle
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    ws = W.config3(512, seed=1)
+    got, B = _batched(ws, tiles=bench.load_tiles(), graph=True)
+    want = _plain(ws)
+    _check(got[0], want, "config 3")
+    first = {}
+    for q, w in enumerate(ws):
+        first.setdefault((w.m, w.d), q)
+    for (m, d), q in sorted(first.items()):
+        print(f"oracle check: instance {q} m={m} d={d} N={ws[q].N}", flush=True)
+        v, g = oracle_lib.eval_workload(ws[q])
+        assert_bitexact(got[0][q][0], v, f"oracle value {q}")
+        assert_bitexact(got[0][q][1], g, f"oracle grad {q}")
