@@ -38,8 +38,8 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one torch copy of this size before timing (for HBM counter calibration)")
     ap.add_argument("--check", action="store_true", help="compare the output digest with the oracle's")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "sweep"],
-                    help="c1: p1 deca double d=152 (the headline); c3: 512-instance batch vs separate launches; "
+    ap.add_argument("--workload", default="p1", choices=["p1", "batch", "sweep"],
+                    help="p1: deca double d=152 (the headline); batch: 512 mixed instances vs separate launches; "
                          "sweep: the paper's precision x degree tables for p1, p2, p3")
     ap.add_argument("--polys", default="p1,p2,p3", help="sweep: test polynomials")
     ap.add_argument("--ms", default="1,2,3,4,5,8,10", help="sweep: precisions")
@@ -47,9 +47,9 @@ def parse():
     ap.add_argument("--complex", action="store_true", help="sweep: complex series")
     ap.add_argument("--emax", type=int, default=1,
                     help="sweep: raise half of the variable occurrences to exponents 2..emax")
-    ap.add_argument("--instances", type=int, default=512, help="c3: number of instances")
+    ap.add_argument("--instances", type=int, default=512, help="batch: number of instances")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched-vs-plain (c3) and autograd (c4) side measurements")
+                    help="skip the side measurements (batched vs plain, autograd, complex, streamed, layering, seeds)")
     return ap.parse_args()
 
 
@@ -63,7 +63,7 @@ def kernel_source_digest():
 def traffic_from_profile(digest, launches_per_step):
     """HBM bytes per convolution launch from the committed PMC summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "conv_layer_kernel_c1_traffic.json")
+    path = os.path.join(ROOT, "profiles", "conv_layer_kernel_p1_10d_d152_traffic.json")
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
@@ -82,7 +82,7 @@ def cpu_baseline(target_s):
     from paper_2101_10881_amd import workloads as W
 
     cores = len(os.sched_getaffinity(0))
-    full = W.config1()
+    full = W.p1()
 
     def sample(K, threads):
         sup = full.supports()[:K]
@@ -109,8 +109,8 @@ def cpu_baseline(target_s):
                               "sample": f"first {K1} monomials, 1 thread ({dt1:.1f} s wall)"}}
 
 
-def measure_c3(instances, steps, warmup):
-    """The batched configuration: `instances` polynomials (n 8..64, N 16..1024,
+def measure_batch(instances, steps, warmup):
+    """The batched workload: `instances` polynomials (n 8..64, N 16..1024,
     2..8 variables per monomial, d in {8,16,32,64,128}, m in {2,4}) in one
     persistent launch (plain and hipGraph-replayed) against one eval_and_diff
     per instance on one stream.  Outputs must agree bit for bit."""
@@ -121,7 +121,7 @@ def measure_c3(instances, steps, warmup):
 
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    ws = W.config3(instances, seed=1)
+    ws = W.mixed_batch(instances, seed=1)
     B = mdpe.BatchedPolynomials(ws, dev, tiles=load_tiles())
     coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
     zs = [torch.from_numpy(w.z).to(dev) for w in ws]
@@ -158,7 +158,7 @@ def measure_c3(instances, steps, warmup):
                for x, y in zip(B.values + B.grads, pv + pg))
     info = B.batch.info()
     return {
-        "workload": f"c3_batch_{instances}", "instances": instances, "seed": 1,
+        "workload": f"mixed_batch_{instances}", "instances": instances, "seed": 1,
         "GFLOPs": round(work / (ms_graph * 1e-3) / 1e9, 1),
         "batched_ms": {"graph": round(ms_graph, 4), "launch": round(ms_batch, 4)},
         "plain_ms": round(ms_plain, 4),
@@ -171,8 +171,8 @@ def measure_c3(instances, steps, warmup):
     }
 
 
-def run_c3(a):
-    r = measure_c3(a.instances, a.steps, a.warmup)
+def run_batch(a):
+    r = measure_batch(a.instances, a.steps, a.warmup)
     out = {
         "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
         "value": r["GFLOPs"], "unit": "GFLOP/s",
@@ -186,8 +186,8 @@ def run_c3(a):
     print(json.dumps(out), flush=True)
 
 
-def measure_c4(steps, warmup):
-    """The differentiation configuration: octo-double p1 at d = 32; forward
+def measure_autograd(steps, warmup):
+    """The differentiation workload: octo-double p1 at d = 32; forward
     (eval_and_diff keeping the monomial products) and the reverse pass."""
     import torch
 
@@ -195,7 +195,7 @@ def measure_c4(steps, warmup):
     from paper_2101_10881_amd import workloads as W
 
     dev = torch.device("cuda", 0)
-    w = W.config4()
+    w = W.p1(m=8, d=32)
     P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
     coeff = torch.from_numpy(w.coeff).to(dev)
     z = torch.from_numpy(w.z).to(dev)
@@ -231,7 +231,7 @@ def measure_complex(steps, warmup, m=10, d=152):
     from paper_2101_10881_amd import workloads as W
 
     dev = torch.device("cuda", 0)
-    w = W.config1(m=m, d=d, cx=True)
+    w = W.p1(m=m, d=d, cx=True)
     P = mdpe.Polynomial.for_workload(w, dev)
     coeff = torch.from_numpy(w.coeff).to(dev)
     z = torch.from_numpy(w.z).to(dev)
@@ -254,7 +254,7 @@ def measure_complex(steps, warmup, m=10, d=152):
 
 def measure_streamed(steps, warmup):
     """Streamed operands (both read from global memory, several wavefronts per
-    job): c1's workload forced to stream (its plan stages), and a large degree
+    job): p1 in deca double at d = 152 forced to stream (its plan stages), and a large degree
     (all 4-subsets of 8 variables, quad double, d = 4000) where the plan
     streams by itself, beside the same plan forced to stage."""
     import torch
@@ -265,7 +265,7 @@ def measure_streamed(steps, warmup):
     dev = torch.device("cuda", 0)
     out = {}
     big = W.make("p_8_4_4d_d4000", 4, 4000, 8, W.all_subsets(8, 4), seed=1)
-    for key, w, force in (("c1_forced", W.config1(), True), ("degree_4000_staged", big, False),
+    for key, w, force in (("p1_10d_d152_forced", W.p1(), True), ("degree_4000_staged", big, False),
                           ("degree_4000", big, None)):
         P = mdpe.Polynomial.for_workload(w, dev, stream_operands=force)
         coeff = torch.from_numpy(w.coeff).to(dev)
@@ -289,16 +289,17 @@ def measure_streamed(steps, warmup):
 
 
 def measure_layering(steps, warmup):
-    """c1 with the earliest-layer layering of Section 5 (MDPE_ASAP_LAYERS:
-    3640/5460/5460/1820 jobs, 18 rounds of the 1024 SIMDs) beside the default
-    balanced one (3072/4096/6144/3068, 16 rounds); outputs compared bitwise."""
+    """p1 in deca double at d = 152 with the earliest-layer layering of
+    Section 5 (MDPE_ASAP_LAYERS: 3640/5460/5460/1820 jobs, 18 rounds of the
+    1024 SIMDs) beside the default balanced one (3072/4096/6144/3068, 16
+    rounds); outputs compared bitwise."""
     import torch
 
     from paper_2101_10881_amd import mdpe
     from paper_2101_10881_amd import workloads as W
 
     dev = torch.device("cuda", 0)
-    w = W.config1()
+    w = W.p1()
     coeff = torch.from_numpy(w.coeff).to(dev)
     z = torch.from_numpy(w.z).to(dev)
     out, bits = {}, []
@@ -322,9 +323,9 @@ def measure_layering(steps, warmup):
 
 
 def measure_seeds(P, steps):
-    """c1's step time for the input seeds 2..10 with the same plan (p1's
-    supports do not depend on the seed; the series values do), the spread the
-    paper reports over seeds (Table 8)."""
+    """The step time of p1 in deca double at d = 152 for the input seeds
+    2..10 with the same plan (p1's supports do not depend on the seed; the
+    series values do), the spread the paper reports over seeds (Table 8)."""
     import torch
 
     from paper_2101_10881_amd import workloads as W
@@ -332,7 +333,7 @@ def measure_seeds(P, steps):
     dev = P.workspace.device
     ms = {}
     for seed in range(2, 11):
-        w = W.config1(seed=seed)
+        w = W.p1(seed=seed)
         coeff = torch.from_numpy(w.coeff).to(dev)
         z = torch.from_numpy(w.z).to(dev)
         v, g = P.eval_and_diff(coeff, z)
@@ -345,13 +346,13 @@ def measure_seeds(P, steps):
         torch.cuda.synchronize()
         ms[seed] = round(e0.elapsed_time(e1) / steps, 4)
     vals = sorted(ms.values())
-    return {"workload": "c1_p1_10d_d152", "steps_per_seed": steps, "ms_per_step": ms,
+    return {"workload": "p1_10d_d152", "steps_per_seed": steps, "ms_per_step": ms,
             "median": vals[len(vals) // 2], "min": vals[0], "max": vals[-1]}
 
 
 def sweep_workload(poly, m, d, cx=False, emax=1):
     from paper_2101_10881_amd import workloads as W
-    w = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
+    w = {"p1": W.p1, "p2": W.p2, "p3": W.p3}[poly](seed=1, m=m, d=d, cx=cx)
     return W.with_exponents(w, emax, seed=1) if emax > 1 else w
 
 
@@ -414,8 +415,8 @@ def main():
                                    "by monomial ranges with one all-gather of partial series; no multi-GPU run "
                                    "is implemented)"}))
         sys.exit(2)
-    if a.workload == "c3":
-        return run_c3(a)
+    if a.workload == "batch":
+        return run_batch(a)
     if a.workload == "sweep":
         return run_sweep(a)
     import torch
@@ -424,7 +425,7 @@ def main():
     from paper_2101_10881_amd import workloads as W
 
     dev = torch.device("cuda", 0)
-    w = W.config1()
+    w = W.p1()
     P = mdpe.Polynomial.for_workload(w, dev)
     info = P.plan.info
     conv_sizes, add_sizes = P.plan.layer_sizes()
@@ -515,13 +516,13 @@ def main():
         "kernel_source_sha256": digest[:16],
     }
     if a.check:
-        g = json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json")))["workloads"]["config1"]
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json")))["workloads"]["p1_10d_d152"]
         h = lambda t: hashlib.sha256(t.cpu().numpy().astype("<f8").tobytes()).hexdigest()
         out["check"] = {"value_matches_oracle_digest": h(value) == g["value_sha256"],
                         "grad_matches_oracle_digest": h(grad) == g["grad_sha256"]}
     if not a.no_extras:
-        out["batched_vs_plain"] = measure_c3(a.instances, 3, 1)
-        out["autograd_c4"] = measure_c4(10, 2)
+        out["batched_vs_plain"] = measure_batch(a.instances, 3, 1)
+        out["autograd_p1_8d_d32"] = measure_autograd(10, 2)
         out["complex_p1"] = measure_complex(5, 1)
         out["streamed_operands"] = measure_streamed(3, 1)
         out["layer_balancing"] = measure_layering(5, 1)

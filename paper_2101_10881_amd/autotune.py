@@ -55,7 +55,7 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    ws = W.config3(a.instances, seed=a.seed)
+    ws = W.mixed_batch(a.instances, seed=a.seed)
     B = mdpe.BatchedPolynomials(ws, dev)
     B.bind([torch.from_numpy(w.coeff).to(dev) for w in ws], [torch.from_numpy(w.z).to(dev) for w in ws])
     stream = torch.cuda.current_stream()

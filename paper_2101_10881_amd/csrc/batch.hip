@@ -71,7 +71,8 @@ __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, in
     const int kind = __builtin_amdgcn_readfirstlane(T.kind);
     if (kind == 1) {
         for (int g = 0; g < T.count; g += I.J) {
-            // chain codes loaded every step: 1.4% faster here (c3) than at chain starts
+            // chain codes loaded every step: 1.4% faster here (512 mixed
+            // instances) than at chain starts
             conv_group<M, false, false, false, true>(I.A, I.conv + T.first + g, min(I.J, T.count - g), I.J, I.d, lds,
                                                      I.chains, I.stride, I.steps, lane, lane, I.simple != 0);
             __syncthreads();

@@ -59,19 +59,21 @@ __host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, i
 // One 64-lane wavefront computes jn <= J jobs jobs[0..jn) (the output
 // coefficients of each spread over the lanes by the schedule `chains`).
 // lds must hold group_lds_bytes(d+1, lds_doubles_per_coef(W), J) bytes (0
-// doubles per coefficient when streamed).  Ends with the wavefront's stores issued (not necessarily complete).
+// doubles per coefficient when streamed).  Ends with the wavefront's stores
+// issued (not necessarily complete).
 // XS = true (streamed operands, for degrees whose operands do not fit in LDS):
 // both operands are read from global memory and only the job descriptors are
 // in LDS; the planner then guarantees that no job writes its first operand.
 // `row` selects the lane's row of the schedule (q*64 + lane for the q-th of
-// the nrows / 64 wavefronts sharing a job).  `simple` (coefficients of at most two
-// doubles, staged operands): deal the coefficients to the lanes in turn
-// instead of following the schedule (see below).
+// the nrows / 64 wavefronts sharing a job).  `simple` (coefficients of at
+// most two doubles, staged operands): deal the coefficients to the lanes in
+// turn instead of following the schedule (see below).
 // CODE_AHEAD: load the code of a lane's next chain at every step, outside
 // the chain-start branch, instead of inside it.  Measured on lone wavefronts
 // (p2's layers): 15-18% faster for jobs spread over several wavefronts
 // (p2 10d, d = 152), 15% slower for groups of several jobs per wavefront
-// (p2 10d, d = 63; c4), equal on c1; the kernel chooses per instantiation.
+// (p2 10d, d = 63; p1 8d, d = 32), equal on p1 10d at d = 152; the kernel
+// chooses per instantiation.
 template <int M, bool CORR, bool CX = false, bool XS = false, bool CODE_AHEAD = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,

@@ -233,7 +233,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
 
 // Relative cost of a layer plan: each layer takes about ceil(wavefronts /
 // SIMDs) wavefront lifetimes (a SIMD's throughput hardly depends on how many
-// wavefronts share it), a streamed step costing ~1.2 staged steps (c1: 15.2
+// wavefronts share it), a streamed step costing ~1.2 staged steps (p1 10d: 15.2
 // vs 12.9 ms at equal steps).
 constexpr long kSimds = 1024;  // MI355X: 256 CUs x 4 SIMDs
 
@@ -641,7 +641,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         // wavefront or several wavefronts per job pay when layers have fewer
         // wavefronts than the chip has SIMDs (deep chains such as p2).
         // (A candidate replaces the default only when estimated 10% faster: the
-        // model ignores staging and per-wavefront costs, e.g. c2's two jobs
+        // model ignores staging and per-wavefront costs, e.g. p2 4d d = 64's two jobs
         // per wavefront measure 4% faster than one although it predicts the
         // opposite.)  Dealt steps weigh 0.15 (m = 1) or 0.4 (m = 2): measured
         // on p2 at d = 152.

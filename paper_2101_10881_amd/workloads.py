@@ -143,7 +143,7 @@ def random_poly(name: str, m: int, d: int, n: int, N: int, nk, seed: int = 1, cx
     return Workload(name, m, d, n, nvars, vars_, coeff, z, {"seed": seed})
 
 
-# ----- the five benchmark configurations ---------------------------------------------------
+# ----- the benchmark workloads ----------------------------------------------------------
 
 def with_exponents(w: Workload, emax: int, seed: int = 1, frac: float = 0.5) -> Workload:
     """The same workload with exponents: each occurrence of a variable gets,
@@ -158,24 +158,20 @@ def _cname(name, cx):
     return name + "_complex" if cx else name
 
 
-def config0(seed: int = 1, cx: bool = False) -> Workload:
+def rand3(seed: int = 1, cx: bool = False) -> Workload:
     """Double double, d=8: n=8, 16 monomials of 3 distinct variables each."""
-    return random_poly(_cname("c0_2d_d8_n8_N16", cx), 2, 8, 8, 16, 3, seed, cx)
+    return random_poly(_cname("rand3_2d_d8_n8_N16", cx), 2, 8, 8, 16, 3, seed, cx)
 
 
-def config1(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
-    """p1 (all 1820 4-subsets of 16 variables), deca double, d=152 (Table 3)."""
-    return make(_cname(f"c1_p1_{m}d_d{d}", cx), m, d, 16, all_subsets(16, 4), seed, {"seed": seed}, cx)
+def p1(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
+    """p1 (all 1820 4-subsets of 16 variables); deca double at d=152 is the
+    workload of Table 3, octo double at d=32 the differentiation one."""
+    return make(_cname(f"p1_{m}d_d{d}", cx), m, d, 16, all_subsets(16, 4), seed, {"seed": seed}, cx)
 
 
-def config2(seed: int = 1, m: int = 4, d: int = 64, cx: bool = False) -> Workload:
+def p2(seed: int = 1, m: int = 4, d: int = 64, cx: bool = False) -> Workload:
     """p2 shape: n=128, 128 monomials of 64 distinct variables, quad double, d=64."""
-    return random_poly(_cname(f"c2_p2_{m}d_d{d}", cx), m, d, 128, 128, 64, seed, cx)
-
-
-def config4(seed: int = 1) -> Workload:
-    """p1 in octo double at d=32 (the differentiation configuration)."""
-    return make("c4_p1_8d_d32", 8, 32, 16, all_subsets(16, 4), seed, {"seed": seed})
+    return random_poly(_cname(f"p2_{m}d_d{d}", cx), m, d, 128, 128, 64, seed, cx)
 
 
 def p3(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
@@ -184,7 +180,7 @@ def p3(seed: int = 1, m: int = 10, d: int = 152, cx: bool = False) -> Workload:
 
 
 def batch_instances(count: int = 512, seed: int = 1):
-    """Instance parameters of the batched configuration (drawn, not built)."""
+    """Instance parameters of the batched workload (drawn, not built)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -206,11 +202,11 @@ def upstream_adjoint(m: int, d: int, seed: int = 1) -> np.ndarray:
     return out
 
 
-def config3(count: int = 512, seed: int = 1):
-    """The batched configuration: `count` instances with parameters drawn by
+def mixed_batch(count: int = 512, seed: int = 1):
+    """The batched workload: `count` instances with parameters drawn by
     batch_instances(count, seed), each built from its own seed."""
     out = []
     for q, par in enumerate(batch_instances(count, seed)):
-        out.append(random_poly(f"c3_{q}_m{par['m']}_d{par['d']}", par["m"], par["d"], par["n"], par["N"],
+        out.append(random_poly(f"batch{q}_m{par['m']}_d{par['d']}", par["m"], par["d"], par["n"], par["N"],
                                par["nk"], par["seed"]))
     return out

@@ -25,7 +25,7 @@ def digest(a) -> str:
 def main():
     out = {"_source": "oracle/oracle.c via tests/golden/make_digests.py; inputs from paper_2101_10881_amd.workloads",
            "workloads": {}}
-    for name, w in (("config1", W.config1()), ("config1_complex", W.config1(cx=True))):
+    for name, w in (("p1_10d_d152", W.p1()), ("p1_10d_d152_complex", W.p1(cx=True))):
         t = time.time()
         val, grad = O.eval_workload(w, nthreads=os.cpu_count())
         out["workloads"][name] = {

@@ -28,7 +28,7 @@ def test_flop_accounting_closed_forms():
     m, d = 10, 152
     assert flops.conv_md_ops(d) == (11781, 11628)
     assert flops.conv_flops(m, d) == 11781 * flops.md_flops("mul", m) + 11628 * flops.md_flops("add", m)
-    assert flops.conv_flops(m, d) == 25588791                 # the figure bench.py reports per c1 job
+    assert flops.conv_flops(m, d) == 25588791                 # the figure bench.py reports per job of p1, deca double, d = 152
     # complex: 4 md_mul + 2 md_add per product, 2 md_add per sum
     assert flops.coef_flops("mul", m, True) == 4 * flops.md_flops("mul", m) + 2 * flops.md_flops("add", m)
     # the paper's convention for deca doubles (Section 6.2) on p1 at d = 152
@@ -37,7 +37,7 @@ def test_flop_accounting_closed_forms():
 
 def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     digest = bench.kernel_source_digest()
-    t = json.load(open(os.path.join(ROOT, "profiles", "conv_layer_kernel_c1_traffic.json")))
+    t = json.load(open(os.path.join(ROOT, "profiles", "conv_layer_kernel_p1_10d_d152_traffic.json")))
     got = bench.traffic_from_profile(digest, 4)
     if t["kernel_source_sha256"] == digest:
         assert got == t["hbm_bytes_per_launch"]

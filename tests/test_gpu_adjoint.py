@@ -68,8 +68,8 @@ def test_adjoint_dealt_over_wavefronts(oracle_lib, m):
     _compare(oracle_lib, w, W.md_series(rng, 1, m, 152)[:, 0, :])
 
 
-def test_config4_adjoint_bitexact(oracle_lib):
-    w = W.config4()
+def test_p1_8d_d32_adjoint_bitexact(oracle_lib):
+    w = W.p1(m=8, d=32)
     _compare(oracle_lib, w, W.upstream_adjoint(w.m, w.d, seed=1))
 
 

@@ -140,7 +140,7 @@ def test_wavefronts_running_many_tasks(grid):
     _check(got[1], want, f"grid {grid} replay")
 
 
-def test_config3_full_size(oracle_lib):
+def test_mixed_batch_512_full_size(oracle_lib):
     # the batched configuration as the benchmark times it: 512 instances,
     # autotuned tiles, one graph launch; every instance bitwise equal to its
     # plain evaluation, and one instance of each (m, d) bucket to the oracle
@@ -148,7 +148,7 @@ def test_config3_full_size(oracle_lib):
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    ws = W.config3(512, seed=1)
+    ws = W.mixed_batch(512, seed=1)
     got, B = _batched(ws, tiles=bench.load_tiles(), graph=True)
     want = _plain(ws)
     _check(got[0], want, "config 3")

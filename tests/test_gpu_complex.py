@@ -77,15 +77,15 @@ def test_complex_edge_cases(oracle_lib):
 
 
 def test_complex_shapes_of_the_test_polynomials(oracle_lib):
-    _compare(oracle_lib, W.config0(cx=True))
-    _compare(oracle_lib, W.config2(m=2, d=16, cx=True))
+    _compare(oracle_lib, W.rand3(cx=True))
+    _compare(oracle_lib, W.p2(m=2, d=16, cx=True))
     _compare(oracle_lib, W.p3(m=2, d=4, cx=True))
 
 
 def test_complex_p1_full_size_digest():
     # p1 in complex deca double at d = 152, against a digest of the oracle's output
-    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["config1_complex"]
-    w = W.config1(cx=True)
+    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["p1_10d_d152_complex"]
+    w = W.p1(cx=True)
     _say(f"complex eval_and_diff {w.name} (digest)")
     val, grad = run_gpu(w)
     assert [float(v).hex() for v in val[..., 0].ravel()] == g["value_head"]

@@ -43,4 +43,4 @@ def test_exponent_edge_cases(oracle_lib):
 
 def test_p1_with_exponents(oracle_lib):
     # p1's supports in quad double at d = 32, half of the occurrences raised to 2..4
-    _compare(oracle_lib, W.with_exponents(W.config1(m=4, d=32), 4, seed=1))
+    _compare(oracle_lib, W.with_exponents(W.p1(m=4, d=32), 4, seed=1))

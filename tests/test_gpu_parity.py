@@ -103,16 +103,16 @@ def test_integer_inputs_exact(oracle_lib):
     _compare(oracle_lib, w)
 
 
-def test_config0_bitexact(oracle_lib):
-    _compare(oracle_lib, W.config0())
+def test_rand3_2d_d8_bitexact(oracle_lib):
+    _compare(oracle_lib, W.rand3())
 
 
-def test_config2_bitexact(oracle_lib):
-    _compare(oracle_lib, W.config2())
+def test_p2_4d_d64_bitexact(oracle_lib):
+    _compare(oracle_lib, W.p2())
 
 
-def test_config4_forward_bitexact(oracle_lib):
-    _compare(oracle_lib, W.config4())
+def test_p1_8d_d32_forward_bitexact(oracle_lib):
+    _compare(oracle_lib, W.p1(m=8, d=32))
 
 
 def test_p3_shape_bitexact(oracle_lib):
@@ -127,7 +127,7 @@ def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     # per workgroup at d = 95; p2 at d >= 152 spreads each job over two
     # wavefronts, dealing the coefficients at m <= 2) and precisions than the
     # benchmark configuration
-    build = {"p1": W.config1, "p2": W.config2, "p3": W.p3}[poly]
+    build = {"p1": W.p1, "p2": W.p2, "p3": W.p3}[poly]
     _compare(oracle_lib, build(m=m, d=d))
 
 
@@ -138,8 +138,8 @@ def test_balanced_layers_bitexact(oracle_lib, case):
     # earliest-layer plan's bits
     import torch
     from paper_2101_10881_amd import mdpe
-    w = {"p1_m2": lambda: W.config1(m=2), "p1_exponents_m2": lambda: W.with_exponents(W.config1(m=2), 3, seed=5),
-         "p1_m3_d32": lambda: W.config1(m=3, d=32), "p1_keep_m1": lambda: W.config1(m=1)}[case]()
+    w = {"p1_m2": lambda: W.p1(m=2), "p1_exponents_m2": lambda: W.with_exponents(W.p1(m=2), 3, seed=5),
+         "p1_m3_d32": lambda: W.p1(m=3, d=32), "p1_keep_m1": lambda: W.p1(m=1)}[case]()
     keep = case.startswith("p1_keep")
     dev = torch.device("cuda", 0)
     bal = mdpe.Polynomial.for_workload(w, dev, keep_monomials=keep)
@@ -171,10 +171,10 @@ def test_maximum_degrees_bitexact(oracle_lib, m, d, cx):
     assert_bitexact(got_g, want_g, f"{w.name} gradient")
 
 
-def test_config1_full_size_digest():
+def test_p1_10d_d152_full_size_digest():
     # full-size deca-double p1 at d = 152, in the launch configuration the benchmark times
-    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["config1"]
-    w = W.config1()
+    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["p1_10d_d152"]
+    w = W.p1()
     _say(f"eval_and_diff {w.name} (digest)")
     val, grad = run_gpu(w)
     assert [float(v).hex() for v in val[:, 0]] == g["value_head"]

@@ -70,8 +70,8 @@ def test_forced_streaming_adjoint(oracle_lib):
 
 def test_forced_streaming_p1_full_size_digest():
     # c1's workload with streamed operands: the same bits as the staged path
-    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["config1"]
-    info, (val, grad) = _run(W.config1(), True)
+    g = json.load(open(os.path.join(GOLD, "digests.json")))["workloads"]["p1_10d_d152"]
+    info, (val, grad) = _run(W.p1(), True)
     assert info["streamed"] == 1
     assert sha256(val) == g["value_sha256"]
     assert sha256(grad) == g["grad_sha256"]

@@ -55,7 +55,7 @@ def test_worked_example():
 def test_p1_counts():
     g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p1"]
     # the paper's launch sizes are those of the earliest-layer layering
-    p = mdpe.Plan.for_workload(W.config1(), device=-1, flags=mdpe.MDPE_ASAP_LAYERS)
+    p = mdpe.Plan.for_workload(W.p1(), device=-1, flags=mdpe.MDPE_ASAP_LAYERS)
     conv, add = p.layer_sizes()
     assert p.info["n_conv"] == g["n_conv"] and p.info["n_add"] == g["n_add"]
     assert conv == g["conv_launches"] and add == g["add_launches"]
@@ -63,7 +63,7 @@ def test_p1_counts():
 
 def test_p2_counts():
     g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p2"]
-    p = mdpe.Plan.for_workload(W.config2(), device=-1)
+    p = mdpe.Plan.for_workload(W.p2(), device=-1)
     conv, add = p.layer_sizes()
     assert p.info["n_conv"] == g["n_conv"] and p.info["n_add"] == g["n_add"]
     assert conv[:31] == [g["first_31_conv_launches"]] * 31
@@ -155,9 +155,10 @@ def test_worked_example_jobs_compute_the_definition():
     assert val == ev and grad == eg
 
 
-@pytest.mark.parametrize("cfg", ["config0", "config1", "config2", "config4"])
-def test_lane_schedule_is_balanced(cfg):
-    w = getattr(W, cfg)()
+@pytest.mark.parametrize("build", [W.rand3, W.p1, W.p2, lambda: W.p1(m=8, d=32)],
+                         ids=["rand3_2d_d8", "p1_10d_d152", "p2_4d_d64", "p1_8d_d32"])
+def test_lane_schedule_is_balanced(build):
+    w = build()
     i = mdpe.Plan.for_workload(w, device=-1).info
     J, d = i["jobs_per_group"], w.d
     total = J * (d + 1) * (d + 2) // 2
@@ -369,21 +370,21 @@ def test_streaming_chosen_by_cost():
     p = mdpe.Plan.for_workload(big, device=-1)
     assert p.info["streamed"] and p.info["waves_per_job"] == 31
     # c1: thousands of jobs per layer, staged
-    assert not mdpe.Plan.for_workload(W.config1(), device=-1).info["streamed"]
+    assert not mdpe.Plan.for_workload(W.p1(), device=-1).info["streamed"]
 
 
-@pytest.mark.parametrize("build,m,d,simple", [(W.config2, 1, 152, 1), (W.config2, 2, 152, 1), (W.config1, 2, 64, 0),
-                                              (W.config2, 4, 152, 0), (W.config1, 10, 152, 0)])
+@pytest.mark.parametrize("build,m,d,simple", [(W.p2, 1, 152, 1), (W.p2, 2, 152, 1), (W.p1, 2, 64, 0),
+                                              (W.p2, 4, 152, 0), (W.p1, 10, 152, 0)])
 def test_simple_dealing_choice(build, m, d, simple):
     # coefficients of at most two doubles are dealt to lanes in turn where the
     # planner estimates it faster than the lane schedule; never for more
     assert mdpe.Plan.for_workload(build(m=m, d=d), device=-1).info["simple_dealing"] == simple
 
 
-@pytest.mark.parametrize("build,m,d,J,Q", [(W.config1, 10, 152, 1, 1), (W.config2, 4, 64, 2, 1),
-                                           (W.config2, 10, 152, 1, 2), (W.config2, 4, 152, 1, 2),
-                                           (W.config2, 1, 152, 1, 2), (W.config2, 2, 95, 1, 2),
-                                           (W.config1, 2, 152, 1, 1)])
+@pytest.mark.parametrize("build,m,d,J,Q", [(W.p1, 10, 152, 1, 1), (W.p2, 4, 64, 2, 1),
+                                           (W.p2, 10, 152, 1, 2), (W.p2, 4, 152, 1, 2),
+                                           (W.p2, 1, 152, 1, 2), (W.p2, 2, 95, 1, 2),
+                                           (W.p1, 2, 152, 1, 1)])
 def test_jobs_and_wavefronts_per_group(build, m, d, J, Q):
     # layers with fewer wavefronts than SIMDs (p2's 378 jobs) spread a job over
     # two wavefronts, down to the longest coefficient's d+1 steps; at one or two

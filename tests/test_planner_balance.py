@@ -83,17 +83,17 @@ def _run_float(p, w):
 
 
 CASES = [
-    ("p1", lambda: W.config1(), 0),
-    ("p1_keep", lambda: W.config1(), mdpe.MDPE_KEEP_MONOMIAL_VALUES),
-    ("p1_streamed", lambda: W.config1(), mdpe.MDPE_STREAM_OPERANDS),
-    ("p1_exponents", lambda: W.with_exponents(W.config1(m=2), 3, seed=5), 0),
-    ("c4", lambda: W.config4(), mdpe.MDPE_KEEP_MONOMIAL_VALUES),
-    ("p1_d32", lambda: W.config1(m=2, d=32), 0),
+    ("p1", lambda: W.p1(), 0),
+    ("p1_keep", lambda: W.p1(), mdpe.MDPE_KEEP_MONOMIAL_VALUES),
+    ("p1_streamed", lambda: W.p1(), mdpe.MDPE_STREAM_OPERANDS),
+    ("p1_exponents", lambda: W.with_exponents(W.p1(m=2), 3, seed=5), 0),
+    ("c4", lambda: W.p1(m=8, d=32), mdpe.MDPE_KEEP_MONOMIAL_VALUES),
+    ("p1_d32", lambda: W.p1(m=2, d=32), 0),
 ]
 
 
 def test_p1_balanced_sizes():
-    asap, bal = _plans(W.config1())
+    asap, bal = _plans(W.p1())
     assert [int(c) for c in asap.layer_sizes()[0]] == [3640, 5460, 5460, 1820]
     assert [int(c) for c in bal.layer_sizes()[0]] == [3072, 4096, 6144, 3068]
     assert (asap.info["balanced_layers"], bal.info["balanced_layers"]) == (0, 1)
@@ -132,7 +132,7 @@ def test_balanced_layering_computes_the_same(name, build, flags):
 def test_a_broken_layering_is_caught_by_the_float_run():
     """The float run is sensitive to a dependency broken by a layering: moving
     one f_2 job a layer earlier (beside the f_1 it reads) changes the result."""
-    w = W.config1(m=1, d=8)
+    w = W.p1(m=1, d=8)
     asap = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_ASAP_LAYERS)
     ref = _run_float(asap, w)
 
@@ -152,7 +152,7 @@ def test_a_broken_layering_is_caught_by_the_float_run():
 
 
 def test_small_layers_keep_the_earliest_layering():
-    for w in (W.config0(), W.config2(), W.p3(m=2)):
+    for w in (W.rand3(), W.p2(), W.p3(m=2)):
         asap, bal = _plans(w)
         assert bal.info["balanced_layers"] == 0
         assert np.array_equal(asap.conv_jobs(), bal.conv_jobs())
