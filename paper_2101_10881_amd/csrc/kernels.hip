@@ -11,10 +11,11 @@
 //   stage_kernel         user coeff / z -> input slots of A (+ n_k = 1 copies)
 //   conv_layer_kernel    one wavefront per group of J jobs of a layer (four per
 //                        workgroup when a launch has one to three wavefronts
-//                        per SIMD) stages the jobs' first operands in LDS (both
-//                        operands for coefficients of at most two doubles; none
-//                        when operands are streamed, with Q wavefronts per
-//                        job) and computes their J*(d+1) output coefficients;
+//                        per SIMD; or Q wavefronts per job, J = 1, for layers
+//                        of few long jobs) stages the jobs' first operands in
+//                        LDS (both operands for coefficients of at most two
+//                        doubles; none when operands are streamed) and
+//                        computes their J*(d+1) output coefficients;
 //                        each coefficient is one lane's sequential chain
 //                        z_k = x_0 y_k, z_k += x_i y_{k-i} (i = 1..k), spread
 //                        over the lanes by a host-made schedule or dealt to the
