@@ -11,11 +11,13 @@
 // with its own L2), balancing estimated cost; all tasks of an instance sit in
 // one queue.  One persistent kernel of one-wavefront workgroups (as many as
 // are resident) reads the XCD it runs on from the XCC_ID hardware register
-// and claims tasks of that XCD's queue with an atomic counter.  So every
-// producer/consumer pair of an instance meets in one L2, and cross-XCD cache
-// coherence is never relied on.  A task of stage s of instance p waits until
-// p's completion counter reaches the number of p's tasks in stages before s
-// (acquire), runs, then increments the counter (release).  Because only
+// and claims tasks of that XCD's queue with an atomic counter, so an
+// instance's data stays near one L2.  A task of stage s of instance p waits
+// until p's completion counter reaches the number of p's tasks in stages
+// before s (agent-scope acquire), runs, then increments the counter
+// (agent-scope release).  The fences are agent-scope because narrower ones
+// are not enough: an L1-only invalidation on acquire and a plain store wait
+// on release gave wrong results.  Because only
 // running wavefronts claim tasks and dependencies point backwards in their
 // queue, the earliest unfinished task of a queue can always run: no deadlock.
 // A bounded spin turns any unexpected wait into an error flag, not a hang.
