@@ -213,11 +213,12 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     double acc[W];
 #pragma unroll
     for (int l = 0; l < W; ++l) acc[l] = 0.0;
-    // Two steps per iteration up to quad double: the copies between the
-    // pipeline's buffers become register renames (m = 4: 60 -> 44 VALU and
-    // 76 -> 48 SALU instructions per step besides the md operations); a
-    // deca-double body is too large to repeat.
-    constexpr int kUnroll = W <= 4 ? 2 : 1;
+    // Two steps per iteration up to five doubles per coefficient: the copies
+    // between the pipeline's buffers become register renames (m = 4: 60 -> 44
+    // VALU and 76 -> 48 SALU instructions per step besides the md
+    // operations).  Measured slower from eight doubles on (octo double: 5-6%
+    // on p2 and at d = 32), where the body is long anyway.
+    constexpr int kUnroll = W <= 5 ? 2 : 1;
 #pragma unroll kUnroll
     for (int s = 0; s < steps; ++s) {
         ChainState n2;
