@@ -201,6 +201,7 @@ struct mdpe_profiler {
     };
     std::vector<Rec> recs;
     size_t used = 0;
+    uint32_t classes = 0xfu;  // bit c: time launches of class c (0 stage, 1 conv, 2 add, 3 gather)
 };
 
 namespace {
@@ -232,7 +233,7 @@ int upload(T **dst, const void *src, size_t bytes) {
 }
 
 int record(mdpe_profiler *prof, int cls, hipStream_t st, bool start) {
-    if (!prof) return MDPE_OK;
+    if (!prof || !((prof->classes >> cls) & 1u)) return MDPE_OK;
     if (start) {
         if (prof->used == prof->recs.size()) {
             mdpe_profiler::Rec r{cls, nullptr, nullptr};
@@ -626,6 +627,14 @@ int profiler_create(mdpe_profiler **out) {
     if (!out) return fail(MDPE_EINVAL, "out is NULL");
     *out = new (std::nothrow) mdpe_profiler();
     return *out ? MDPE_OK : fail(MDPE_ENOMEM, "host allocation failed");
+}
+
+int profiler_set_classes(mdpe_profiler *prof, uint32_t classes) {
+    if (!prof) return fail(MDPE_EINVAL, "profiler is NULL");
+    if (classes & ~0xfu) return fail(MDPE_EINVAL, "unknown launch classes");
+    if (prof->used) return fail(MDPE_EINVAL, "read the recorded events first");
+    prof->classes = classes;
+    return MDPE_OK;
 }
 
 int profiler_read(mdpe_profiler *prof, mdpe_times *o) {

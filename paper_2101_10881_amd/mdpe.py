@@ -102,6 +102,7 @@ def lib():
     L.profiler_create.argtypes = [ctypes.POINTER(_vp)]
     L.profiler_read.argtypes = [_vp, ctypes.POINTER(Times)]
     L.profiler_destroy.argtypes = [_vp]
+    L.profiler_set_classes.argtypes = [_vp, ctypes.c_uint32]
     L.profiler_destroy.restype = None
     L.md_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp]
     L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
@@ -235,11 +236,19 @@ def eval_and_diff(plan: Plan, coeff, z, value, grad, workspace, stream=None):
                                _stream(stream)))
 
 
+MDPE_TIME_STAGE, MDPE_TIME_CONV, MDPE_TIME_ADD, MDPE_TIME_GATHER = 1, 2, 4, 8
+
+
 class Profiler:
-    def __init__(self):
+    """HIP-event timing of the launches of eval_and_diff / eval_adjoint.
+    classes: mask of MDPE_TIME_* (None: all launches)."""
+
+    def __init__(self, classes=None):
         h = _vp()
         _check(lib().profiler_create(ctypes.byref(h)))
         self._h = h
+        if classes is not None:
+            _check(lib().profiler_set_classes(h, int(classes)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -39,6 +39,15 @@ def test_profiler_lifecycle_without_gpu():
     del prof
 
 
+def test_profiler_classes():
+    # a mask of launch classes; unknown bits are refused without touching a GPU
+    p = mdpe.Profiler(classes=mdpe.MDPE_TIME_CONV | mdpe.MDPE_TIME_ADD)
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Profiler(classes=16)
+    assert e.value.code == mdpe.MDPE_EINVAL
+    assert p.read()["n_cnv"] == 0
+
+
 def test_plan_info_fields():
     p = mdpe.Plan(5, [3, 2], [0, 1, 4, 2, 3], 7, 4, device=-1)
     i = p.info

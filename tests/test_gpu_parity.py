@@ -214,6 +214,19 @@ def test_profiled_and_side_stream(oracle_lib):
     assert_bitexact(got[1], want_g, "grad")
 
 
+def test_profiler_conv_launches_only(oracle_lib):
+    # timing only the convolution launches: the same outputs, no other events
+    from paper_2101_10881_amd import mdpe
+    w = W.random_poly("profc", 4, 33, 7, 30, [5] * 30, seed=15)
+    prof = mdpe.Profiler(classes=mdpe.MDPE_TIME_CONV)
+    got = run_gpu(w, profiler=prof)
+    t = prof.read()
+    assert t["n_cnv"] == 5 and t["n_stage"] == t["n_add"] == t["n_gather"] == 0 and t["cnv_ms"] > 0
+    want_v, want_g = oracle_lib.eval_workload(w)
+    assert_bitexact(got[0], want_v, "value")
+    assert_bitexact(got[1], want_g, "grad")
+
+
 def test_hip_graph_capture_and_replay(oracle_lib):
     # the plain path launches kernels only (no allocation, no memset, no
     # synchronisation), so a caller can capture it in a HIP graph; every
