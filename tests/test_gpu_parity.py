@@ -121,12 +121,14 @@ def test_p3_shape_bitexact(oracle_lib):
 
 
 @pytest.mark.parametrize("poly,m,d", [("p1", 1, 191), ("p1", 5, 95), ("p2", 2, 31), ("p3", 8, 15), ("p1", 2, 64),
-                                      ("p2", 2, 152), ("p2", 3, 152), ("p2", 1, 152), ("p2", 1, 191)])
+                                      ("p2", 2, 152), ("p2", 3, 152), ("p2", 1, 152), ("p2", 1, 191),
+                                      ("p2", 1, 64), ("p2", 2, 66)])
 def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     # points of the precision x degree sweep: other lane schedules (two jobs
     # per workgroup at d = 95; p2 at d >= 152 spreads each job over two
-    # wavefronts, dealing the coefficients at m <= 2) and precisions than the
-    # benchmark configuration
+    # wavefronts, dealing the coefficients at m <= 2, and at d = 64 the second
+    # wavefront deals a single coefficient) and precisions than the benchmark
+    # configuration
     build = {"p1": W.p1, "p2": W.p2, "p3": W.p3}[poly]
     _compare(oracle_lib, build(m=m, d=d))
 
