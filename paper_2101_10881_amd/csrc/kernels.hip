@@ -283,6 +283,9 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        if constexpr (mdpe::kCoef<M, CX> <= 2)
+            HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_layer_kernel<M, CORR, CX, 4, false, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set[dv].store(true);
     }
     if (nj == 0) return MDPE_OK;
@@ -307,7 +310,19 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
         const int wpb =
             (waves > simds && waves <= 3 * simds && 4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes) ? 4 : 1;
         const long blocks = (waves + wpb - 1) / wpb;
-        if (Q > 1)
+        // Jobs over Q wavefronts whose coefficients (of at most two doubles)
+        // are dealt: four-wavefront workgroups, so that no SIMD gets two of
+        // them while another idles (p2 2d, d = 64: 1.09 -> 0.78 ms).  Other
+        // multi-wavefront plans measured equal or slower that way (deca
+        // double +22%: the 256-thread bound slows a lone wavefront).
+        const bool dealt4 = mdpe::kCoef<M, CX> <= 2 && Q > 1 && P.simple &&
+                            4 * group_bytes <= (size_t)mdpe::kMaxLdsBytes;
+        if (dealt4) {
+            if constexpr (mdpe::kCoef<M, CX> <= 2)
+                hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 4, false, true>),
+                                   dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * group_bytes, st, A, jobs, nj, P.d,
+                                   J, pl->d_chains, P.lanes.stride, P.lanes.steps, (int)group_bytes, Q, 1);
+        } else if (Q > 1)
             hipLaunchKernelGGL((mdpe::conv_layer_kernel<M, CORR, CX, 1, false, true>), dim3((unsigned)waves), dim3(64),
                                group_bytes, st, A, jobs, nj, P.d, J, pl->d_chains, P.lanes.stride, P.lanes.steps,
                                (int)group_bytes, Q, P.simple ? 1 : 0);
