@@ -217,8 +217,10 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     // between the pipeline's buffers become register renames (m = 4: 60 -> 44
     // VALU and 76 -> 48 SALU instructions per step besides the md
     // operations).  Measured slower from eight doubles on (octo double: 5-6%
-    // on p2 and at d = 32), where the body is long anyway.
-    constexpr int kUnroll = W <= 5 ? 2 : 1;
+    // on p2 and at d = 32), where the body is long anyway, and at five with
+    // jobs over several wavefronts (penta double p2, d = 152: 8.39 -> 8.96 ms,
+    // while one-wavefront groups gain 2-6%).
+    constexpr int kUnroll = (W <= 4 || (W == 5 && !CODE_AHEAD)) ? 2 : 1;
 #pragma unroll kUnroll
     for (int s = 0; s < steps; ++s) {
         ChainState n2;
