@@ -159,3 +159,50 @@ def max_scaled_error(got_planar, exact, mag):
             continue
         worst = max(worst, err / mag[c])
     return worst
+
+
+def permutation_symmetry_holds(eval_workload, m: int, d: int, seed: int) -> bool:
+    """p1 (every product of four of 16 variables) with one coefficient series
+    shared by all monomials is a symmetric function of its variables.  So
+    evaluating at the permuted inputs z'_i = z_{pi(i)} must give the same value
+    and dp/dz'_i = dp/dz_{pi(i)} at the original inputs.  The summation order
+    differs between the two runs, so each result is compared within twice the
+    bound 4(d+1) 2^(-52m), relative to the magnitude series (computed here in
+    float64 from the leading limbs, padded for its own rounding).  Exact
+    differences of the multiple doubles are taken with fractions."""
+    import dataclasses
+    from paper_2101_10881_amd import workloads as W
+    w = W.p1(seed=seed, m=m, d=d)
+    w.coeff[:, 2:, :] = w.coeff[:, 1:2, :]            # a_1 = ... = a_N; a_0 stays its own
+    pi = np.random.default_rng(seed).permutation(w.n)
+    w_perm = dataclasses.replace(w, z=np.ascontiguousarray(w.z[:, pi, :]))
+    val, grad = eval_workload(w)
+    val_p, grad_p = eval_workload(w_perm)
+    # magnitude series from |leading limbs|
+    trunc = lambda x, y: np.convolve(x, y)[: d + 1]
+    a = np.abs(w.coeff[0])
+    z = np.abs(w.z[0])
+    mag_val = a[0].copy()
+    mag_grad = np.zeros((w.n, d + 1))
+    for k, s in enumerate(w.supports()):
+        t = a[k + 1]
+        for j in s:
+            t = trunc(t, z[j])
+        mag_val += t
+        for i in s:
+            g = a[k + 1]
+            for j in s:
+                if j != i:
+                    g = trunc(g, z[j])
+            mag_grad[i] += g
+    tol = 2 * bound(m, d) * Fraction(1 + 2 ** -30)
+
+    def close(x, y, mag):
+        for c in range(d + 1):
+            if abs(md_value(x[:, c]) - md_value(y[:, c])) > tol * Fraction(float(mag[c])):
+                return False
+        return True
+
+    if not close(val, val_p, mag_val):
+        return False
+    return all(close(grad_p[:, i, :], grad[:, pi[i], :], mag_grad[pi[i]]) for i in range(w.n))

@@ -12,6 +12,9 @@ Everything here is checked against something other than the oracle itself:
 * Euler's identity for homogeneous polynomials, sum_i z_i * dp/dz_i = r p,
   which ties the gradient (backward and cross products) to the value
   (forward products);
+* permutation symmetry of p1 (Section 6.1) with one coefficient series for
+  every monomial: permuted inputs give the same value and the permuted
+  gradient, within twice the bound;
 * the pairwise addition tree against the paper's worked example (Section 4,
   the two steps after eq. (5)) and against the eleven addition launch sizes
   printed for p1 in Section 6.1.
@@ -184,3 +187,10 @@ def test_tree_launch_sizes_match_p1(oracle_lib):
     total = [val[i] + 16 * (gr[i] if i < len(gr) else 0) for i in range(len(val))]
     assert total == [4542, 2279, 1140, 562, 281, 140, 78, 39, 20, 2, 1]
     assert sum(total) == 9084
+
+
+@pytest.mark.parametrize("m,d", [(1, 4), (2, 3), (3, 3), (10, 2)])
+def test_p1_permutation_symmetry(oracle_lib, m, d):
+    # p1 with equal a_k is symmetric in its 16 variables: permuting the inputs
+    # leaves the value and permutes the gradient (Section 6.1's p1 shape)
+    assert E.permutation_symmetry_holds(oracle_lib.eval_workload, m, d, seed=3)

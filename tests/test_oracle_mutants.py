@@ -87,8 +87,7 @@ def test_unmutated_oracle_passes_battery(oracle_lib):
     assert _pins_pass(O.lib())
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_mutant_is_caught(tmp_path, name):
+def _build_mutant(tmp_path, name):
     src = open(obuild.SRC).read()
     old, new = MUTANTS[name]
     assert src.count(old) >= 1, f"mutation site for {name} not found"
@@ -97,5 +96,19 @@ def test_mutant_is_caught(tmp_path, name):
     c.write_text(mutant)
     so = tmp_path / "libmutant.so"
     subprocess.run(["gcc", *obuild.CFLAGS, str(c), "-o", str(so), "-lm"], check=True)
-    L = O.bind(str(so))
+    return O.bind(str(so))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    L = _build_mutant(tmp_path, name)
     assert not _pins_pass(L), f"planted mistake {name} was not caught"
+
+
+@pytest.mark.parametrize("name", ["forward_chain_wrong_variable", "backward_start_wrong",
+                                  "cross_product_off_by_one", "last_partial_misassigned"])
+def test_structural_mutant_breaks_permutation_symmetry(tmp_path, name):
+    """The symmetry pin, with no exact reference at all, also rejects the
+    mistakes that depend on a variable's position inside its monomial."""
+    L = _build_mutant(tmp_path, name)
+    assert not E.permutation_symmetry_holds(lambda w: O.eval_workload(w, L=L), 2, 3, seed=3)
