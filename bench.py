@@ -82,6 +82,12 @@ def cpu_baseline(target_s):
     from paper_2101_10881_amd import workloads as W
 
     cores = len(os.sched_getaffinity(0))
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     full = W.p1()
 
     def sample(K, threads):
@@ -101,7 +107,7 @@ def cpu_baseline(target_s):
     # one thread, on a few monomials (a couple of seconds)
     K1 = 48
     dt1, work1 = sample(K1, 1)
-    return {"value": work / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+    return {"value": work / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "cpu_model": cpu_model, "kind": "oracle",
             "sample": f"first {K} of the 1820 monomials of p1, m=10, d=152, seed 1 ({dt:.1f} s wall, "
                       f"{cores} OpenMP threads, same flop accounting as value)",
             "seconds": dt,
