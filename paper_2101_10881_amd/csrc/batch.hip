@@ -9,7 +9,9 @@
 //
 // Instances are spread over one queue per XCD (the MI355X has 8 XCDs, each
 // with its own L2), balancing estimated cost; all tasks of an instance sit in
-// one queue.  One persistent kernel of one-wavefront workgroups (as many as
+// one queue, except for an instance costing more than an eighth of the batch
+// (a batch of one), whose tasks are dealt over all queues in turn.  Each
+// queue is ordered by pipeline depth.  One persistent kernel of one-wavefront workgroups (as many as
 // are resident) reads the XCD it runs on from the XCC_ID hardware register
 // and claims tasks of that XCD's queue with an atomic counter, so an
 // instance's data stays near one L2.  A task of stage s of instance p waits
@@ -17,9 +19,12 @@
 // before s (agent-scope acquire), runs, then increments the counter
 // (agent-scope release).  The fences are agent-scope because narrower ones
 // are not enough: an L1-only invalidation on acquire and a plain store wait
-// on release gave wrong results.  Because only
-// running wavefronts claim tasks and dependencies point backwards in their
-// queue, the earliest unfinished task of a queue can always run: no deadlock.
+// on release gave wrong results; they also make a dealt instance's results
+// visible across XCDs.  No deadlock: a task depends only on tasks of smaller
+// depth, and every queue is claimed in depth order by running wavefronts (each
+// XCD has resident ones), so an unfinished task of the smallest depth is
+// either running with all its inputs done or is reached by its queue once the
+// claimed tasks before it, of the same depth, finish.
 // A bounded spin turns any unexpected wait into an error flag, not a hang.
 #include <hip/hip_runtime.h>
 
@@ -184,7 +189,8 @@ struct mdpe_batch {
     int *d_qinfo = nullptr;
     int *d_ctl = nullptr;
     std::vector<int> qinfo;      // [2 * kQueues]: first task, task count per queue
-    std::vector<int> inst_queue; // queue of each instance
+    std::vector<int> inst_queue; // queue of each instance, -1: dealt over all queues
+    std::vector<int> task_queue; // queue of each task, in task order
     std::vector<int *> d_chains;
     size_t lds = 0;
     int grid = 0;
@@ -333,9 +339,20 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
     std::vector<int> order_p(count);
     for (int p = 0; p < count; ++p) order_p[p] = p;
     std::stable_sort(order_p.begin(), order_p.end(), [&](int a, int c) { return icost[a] > icost[c]; });
+    // An instance costing more than one queue's fair share (a batch of one, or
+    // a few large instances) has its tasks dealt over all queues in turn, so it
+    // runs on every XCD; the others keep one queue each, near one L2.
+    double total = 0;
+    for (double c : icost) total += c;
     std::vector<double> qload(mdpe::kQueues, 0.0);
     B->inst_queue.assign(count, 0);
+    for (int p : order_p)
+        if (icost[p] > total / mdpe::kQueues) {
+            B->inst_queue[p] = -1;
+            for (auto &l : qload) l += icost[p] / mdpe::kQueues;
+        }
     for (int p : order_p) {
+        if (B->inst_queue[p] < 0) continue;
         int best = 0;
         for (int q = 1; q < mdpe::kQueues; ++q)
             if (qload[q] < qload[best]) best = q;
@@ -355,8 +372,11 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
             scheds.push_back(mdpe::make_lane_schedule(P.d, J));
         }
         const mdpe::LaneSchedule &S = scheds[sched_index[key]];
-        const int G = t.groups_per_task > 0 ? t.groups_per_task : std::max(1, (256 + S.steps - 1) / S.steps);
-        const long items_per_task = t.add_items_per_task > 0 ? t.add_items_per_task : 4096;
+        // a dealt instance finds its parallelism inside its own layers: one
+        // group of jobs per task, small addition tasks
+        const bool dealt = B->inst_queue[p] < 0;
+        const int G = dealt ? 1 : t.groups_per_task > 0 ? t.groups_per_task : std::max(1, (256 + S.steps - 1) / S.steps);
+        const long items_per_task = dealt ? 1024 : t.add_items_per_task > 0 ? t.add_items_per_task : 4096;
         lds = std::max(lds, (size_t)mdpe::group_lds_bytes(P.d + 1, mdpe::lds_doubles_per_coef(P.m), J));
         if (lds > (size_t)mdpe::kMaxLdsBytes)
             return bfail(MDPE_EUNSUPPORTED, "a tile's jobs_per_group needs more LDS than one workgroup has");
@@ -379,7 +399,8 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
         const int queue = B->inst_queue[p];
         int depth = 0, done_before = 0, order = 0;
         auto emit = [&](int kind, long first, int cnt, int need) {
-            tmp.push_back({queue, depth, cost, order++, {p, kind, need, cnt, first}});
+            const int q = queue >= 0 ? queue : (p + order) % mdpe::kQueues;
+            tmp.push_back({q, depth, cost, order++, {p, kind, need, cnt, first}});
         };
         auto items = [&](int kind, long total) {
             int n = 0;
@@ -415,6 +436,7 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
     B->qinfo.assign(2 * mdpe::kQueues, 0);
     for (size_t q = 0; q < tmp.size(); ++q) {
         B->tasks.push_back(tmp[q].t);
+        B->task_queue.push_back(tmp[q].queue);
         B->qinfo[mdpe::kQueues + tmp[q].queue]++;
     }
     for (int q = 1; q < mdpe::kQueues; ++q) B->qinfo[q] = B->qinfo[q - 1] + B->qinfo[mdpe::kQueues + q - 1];
@@ -486,7 +508,7 @@ int batch_tasks(const mdpe_batch *b, int32_t *rows) {
         rows[6 * q + 2] = t.need;
         rows[6 * q + 3] = t.count;
         rows[6 * q + 4] = (int32_t)t.first;
-        rows[6 * q + 5] = b->inst_queue[t.inst];
+        rows[6 * q + 5] = b->task_queue[q];
     }
     return MDPE_OK;
 }

@@ -1,8 +1,9 @@
-"""Host-only checks of the batched executor's task queue (no GPU):
-every job and addition item is covered exactly once, each instance's tasks
-appear in pipeline order, and every task waits only for tasks of its own
-instance that come earlier in the queue -- the property that makes the
-persistent kernel deadlock-free."""
+"""Host-only checks of the batched executor's task queues (no GPU):
+every job and addition item is covered exactly once, each queue is ordered by
+pipeline depth, and every task waits only for tasks of its own instance of
+smaller depth -- the property that makes the persistent kernel deadlock-free.
+An instance costing more than an eighth of the batch is dealt over all eight
+queues; the others keep one queue each."""
 import numpy as np
 import pytest
 
@@ -13,6 +14,27 @@ from paper_2101_10881_amd import workloads as W
 def _batch(ws, tiles=None):
     plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
     return plans, mdpe.Batch(plans, tiles)
+
+
+def _depths(rows):
+    """Pipeline depth of each task within its instance: the rank of its wait
+    count among the instance's distinct wait counts (one per stage)."""
+    dep = np.zeros(len(rows), dtype=int)
+    for p in np.unique(rows[:, 0]):
+        idx = np.flatnonzero(rows[:, 0] == p)
+        rank = {v: i for i, v in enumerate(sorted(set(rows[idx, 2].tolist())))}
+        dep[idx] = [rank[v] for v in rows[idx, 2].tolist()]
+    return dep
+
+
+def _check_deadlock_free(rows):
+    dep = _depths(rows)
+    assert list(rows[:, 5]) == sorted(rows[:, 5])          # queues are contiguous, in order
+    for q in np.unique(rows[:, 5]):
+        assert np.all(np.diff(dep[rows[:, 5] == q]) >= 0)   # each queue in depth order
+    for i, r in enumerate(rows):                            # waits for smaller depths only
+        mine = rows[:, 0] == r[0]
+        assert r[2] == np.sum(mine & (dep < dep[i]))
 
 
 @pytest.mark.parametrize("tiles", [None, [{"m": 2, "d": 8, "jobs_per_group": 5, "groups_per_task": 3,
@@ -29,18 +51,13 @@ def test_queue_covers_and_orders(tiles):
     plans, B = _batch(ws, tiles)
     rows = B.tasks()
     assert B.info()["m1"] == 2 and B.info()["m2"] == 4
-    seen_before = {}
-    queue_of = {}
-    for inst, kind, need, count, first, queue in rows:
-        # waits only for earlier tasks of its own instance, all in one queue
-        assert need <= seen_before.get(inst, 0)
-        seen_before[inst] = seen_before.get(inst, 0) + 1
-        assert queue_of.setdefault(inst, queue) == queue
-    assert list(rows[:, 5]) == sorted(rows[:, 5])
+    _check_deadlock_free(rows)
+    dep = _depths(rows)
+    assert len(np.unique(rows[:, 5])) == 8
     for p, w in enumerate(ws):
         mine = rows[rows[:, 0] == p]
-        kinds = list(mine[:, 1])
-        assert kinds == sorted(kinds, key=lambda k: {0: 0, 1: 1, 2: 2, 3: 3}[k])
+        kinds = mine[np.argsort(dep[rows[:, 0] == p], kind="stable"), 1]
+        assert np.all(np.diff(kinds) >= 0)                 # stage, conv, add, gather by depth
         # need = number of this instance's tasks of earlier stages
         info = plans[p].info
         d1 = w.d + 1
@@ -66,3 +83,25 @@ def test_batch_rejects_mixed_precisions():
     with pytest.raises(mdpe.MdpeError) as e:
         _batch(ws)
     assert e.value.code == mdpe.MDPE_EUNSUPPORTED
+
+
+def test_batch_of_one_is_dealt_over_every_queue():
+    for w in (W.p2(m=1, d=8), W.p1(m=2, d=8)):
+        _, B = _batch([w])
+        rows = B.tasks()
+        _check_deadlock_free(rows)
+        per_queue = np.bincount(rows[:, 5], minlength=8)
+        assert len(per_queue) == 8 and per_queue.max() - per_queue.min() <= 1
+        conv = rows[rows[:, 1] == 1]
+        J = B.info()["n_conv_tasks"]
+        assert J == len(conv) and conv[:, 3].max() <= 16   # one group of jobs per task
+
+
+def test_equal_instances_keep_one_queue_each():
+    ws = [W.random_poly(f"e{q}", 2, 8, 6, 20, 3, seed=1) for q in range(16)]
+    _, B = _batch(ws)
+    rows = B.tasks()
+    _check_deadlock_free(rows)
+    for p in range(16):
+        assert len(np.unique(rows[rows[:, 0] == p, 5])) == 1
+    assert np.all(np.bincount(rows[:, 5], minlength=8) > 0)

@@ -160,3 +160,22 @@ def test_mixed_batch_512_full_size(oracle_lib):
         v, g = oracle_lib.eval_workload(ws[q])
         assert_bitexact(got[0][q][0], v, f"oracle value {q}")
         assert_bitexact(got[0][q][1], g, f"oracle grad {q}")
+
+
+@pytest.mark.parametrize("name,build,grid", [
+    ("p2_1d_d8", lambda: W.p2(m=1, d=8), 0),
+    ("p2_2d_d64", lambda: W.p2(m=2, d=64), 0),
+    ("p2_4d_d64", lambda: W.p2(), 0),
+    ("p1_4d_d8", lambda: W.p1(m=4, d=8), 0),
+    ("rand3_2d_d8", lambda: W.rand3(), 0),
+    ("p2_1d_d8_grid8", lambda: W.p2(m=1, d=8), 8),
+])
+def test_batch_of_one_dealt_over_every_xcd(name, build, grid):
+    # one instance is dealt over all eight XCD queues; each layer's results
+    # cross XCDs through the agent-scope fences
+    ws = [build()]
+    want = _plain(ws)
+    got, B = _batched(ws, graph=True, replays=2, grid=grid)
+    assert len(np.unique(B.batch.tasks()[:, 5])) == 8
+    _check(got[0], want, name)
+    _check(got[1], want, name + " replay")
