@@ -256,11 +256,14 @@ int md_elementwise(int op, int m, int64_t count, const double *x, const double *
  * (which must outlive it); each instance keeps its own buffers.  All stages
  * of all instances (staging, convolution layers, addition levels, gather)
  * become tasks; each instance goes whole to one of 8 queues, one per XCD,
- * balanced by estimated cost, ordered by pipeline depth.  One persistent
- * kernel of one-wavefront workgroups claims the tasks of the XCD it runs on,
- * and a task waits (acquire) on a per-instance completion counter for the
- * stages before its own, so producers and consumers of an instance always
- * share one L2.  Bits are identical to eval_and_diff of each instance.
+ * balanced by estimated cost, so that producers and consumers of an instance
+ * share one L2 -- except an instance whose estimated cost exceeds an eighth
+ * of the batch (a batch of one), whose tasks, one group of jobs each, are
+ * dealt over all queues in turn.  Every queue is ordered by pipeline depth.
+ * One persistent kernel of one-wavefront workgroups claims the tasks of the
+ * XCD it runs on, and a task waits (agent-scope acquire) on a per-instance
+ * completion counter for the stages before its own.  Bits are identical to
+ * eval_and_diff of each instance.
  * Precisions in one batch: all equal, or {2, 4}.
  */
 typedef struct mdpe_batch mdpe_batch;
