@@ -396,6 +396,7 @@ def run_sweep(a):
                 row = {"poly": poly, "complex": a.complex, "emax": a.emax, "m": m, "d": d, "cnv_ms": round(t["cnv_ms"] / reps, 4),
                        "add_ms": round(t["add_ms"] / reps, 4), "sum_ms": round((t["cnv_ms"] + t["add_ms"]) / reps, 4),
                        "wall_ms": round(wall, 4), "n_conv": info["n_conv"], "n_add": info["n_add"],
+                       "fused_layers": int(info["fused_components"] > 0),
                        "TFLOPs": round(work / (t["cnv_ms"] + t["add_ms"]) * reps / 1e9, 3)}
                 rows.append(row)
                 print(json.dumps(row), flush=True)

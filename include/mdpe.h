@@ -112,6 +112,26 @@ typedef struct {
  * job after the jobs it depends on gives the same output bits. */
 #define MDPE_ASAP_LAYERS 16u
 
+/* Plan flag: run every convolution layer in one launch (plans do so by
+ * themselves where it is estimated faster: deep plans of layers under 512
+ * jobs, one wavefront per job, d <= 127 up to four doubles per coefficient,
+ * d <= 15 beyond; MDPE_LAYER_LAUNCHES keeps one launch per layer).  The jobs fall into
+ * independent components -- no slot written by a job of one component is read
+ * or written by a job of another (for multilinear polynomials, one component
+ * per monomial) -- and one workgroup runs a component's layers in order, with
+ * a workgroup barrier between layers, one job per wavefront at a time.  For
+ * deep chains of small layers (many variables per monomial, few monomials)
+ * this replaces one kernel boundary per layer, each costing a few
+ * microseconds, by a barrier.  Each job's arithmetic, hence every output bit,
+ * is that of the per-layer launches.  Ignored for streamed-operand plans
+ * (mdpe_plan_info.fused_components is then 0); the batched executor keeps its
+ * own schedule. */
+#define MDPE_FUSED_LAYERS 32u
+
+/* Plan flag: one launch per convolution layer, never fused (excludes
+ * MDPE_FUSED_LAYERS). */
+#define MDPE_LAYER_LAUNCHES 64u
+
 /* Plan summary. */
 typedef struct {
     int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
@@ -133,6 +153,10 @@ typedef struct {
                                instead of following the lane schedule */
     int32_t balanced_layers;/* 1 if convolutions with slack were moved to later layers (see
                                MDPE_ASAP_LAYERS) */
+    int32_t fused_components;/* MDPE_FUSED_LAYERS: independent components, one workgroup each
+                               (0 when the layers are launched one by one) */
+    int32_t fused_waves;    /* MDPE_FUSED_LAYERS: wavefronts per component workgroup (at most 4;
+                               fewer at launch where their LDS would not fit) */
 } mdpe_plan_info;
 
 /*
@@ -157,6 +181,12 @@ int plan_layer_sizes(const mdpe_plan *plan, int32_t *conv_sizes, int32_t *add_si
  * array A); job meaning A[t3] := A[t1] * A[t2].  rows: int32[n_conv][4], in
  * launch order. */
 int plan_conv_jobs(const mdpe_plan *plan, int32_t *rows);
+
+/* MDPE_FUSED_LAYERS plans: the convolution jobs as rows {component, layer
+ * (1-based), t1, t2, t3}, grouped by component, then layer, in the order the
+ * fused launch runs them.  rows: int32[n_conv][5].  MDPE_EINVAL for a plan
+ * without fused layers. */
+int plan_fused_jobs(const mdpe_plan *plan, int32_t *rows);
 
 /* Addition jobs as rows {level (1-based), t1, t2}: A[t2] := A[t2] + A[t1].
  * rows: int32[n_add][3], in launch order. */

@@ -277,6 +277,38 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
                                     chains, stride, steps, lane, part * 64 + lane, simple != 0, (MQ ? Q : 1) * 64);
 }
 
+// Every convolution layer of a plan in one launch.  The jobs fall into
+// independent components (no slot written by a job of one is read or written
+// by a job of another), and a component's jobs depend only on its own earlier
+// layers.  Workgroup c runs component c layer by layer: in each round its
+// wavefronts take one job each (wavefront w the w-th of the round), and a
+// workgroup barrier ends every layer, after which the layer's stores are
+// visible to the whole workgroup.  Every wavefront runs the same rounds (a
+// wavefront without a job still meets conv_group's barrier), so the barriers
+// match.  Each job runs exactly as in conv_layer_kernel with one job per
+// group, so the output bits are those of the per-layer launches.
+template <int M, bool CX = false>
+__global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                          const int *__restrict__ off, int nl, int d,
+                                                          const int *__restrict__ chains, int stride, int steps,
+                                                          int group_bytes, int simple) {
+    extern __shared__ double lds[];
+    const int waves = (int)(blockDim.x >> 6);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int *o = off + (long)blockIdx.x * (nl + 1);
+    double *mine = (double *)((char *)lds + wave * group_bytes);
+    for (int L = 0; L < nl; ++L) {
+        const int a = o[L], b = o[L + 1];
+        for (int r = a; r < b; r += waves) {
+            const int q = r + wave;
+            conv_group<M, false, CX, false, false>(A, jobs + (q < b ? q : a), q < b ? 1 : 0, 1, d, mine, chains,
+                                                   stride, steps, lane, lane, simple != 0);
+        }
+        __syncthreads();
+    }
+}
+
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).
 template <int M, bool CX = false>
 __device__ __forceinline__ void add_item(double *__restrict__ A, int2 t, int c, int d) {

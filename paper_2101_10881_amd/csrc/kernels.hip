@@ -220,6 +220,9 @@ void free_plan(mdpe_plan *p) {
         (void)hipFree(p->d_zbar);
         (void)hipFree(p->d_ybar);
         (void)hipFree(p->d_scale);
+        (void)hipFree(p->d_fconv);
+        (void)hipFree(p->d_foff);
+        (void)hipFree(p->d_fchains);
     }
     delete p;
 }
@@ -339,9 +342,34 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
     return record(prof, 1, st, false);
 }
 
+// fused layers: one workgroup per component, up to four wavefronts each
+// (fewer where their LDS would not fit)
+template <int M, bool CX>
+int launch_fused(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    const size_t group_bytes = (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), 1) + 15) / 16 * 16;
+    int waves = P.fused_waves;
+    while (waves > 1 && waves * group_bytes > (size_t)mdpe::kMaxLdsBytes) --waves;
+    static std::atomic<bool> attr_set[kMaxDevices];
+    const int dv = pl->device >= 0 && pl->device < kMaxDevices ? pl->device : 0;
+    if (!attr_set[dv].load()) {
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_fused_kernel<M, CX>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        attr_set[dv].store(true);
+    }
+    int rc = record(prof, 1, st, true);
+    if (rc) return rc;
+    hipLaunchKernelGGL((mdpe::conv_fused_kernel<M, CX>), dim3((unsigned)P.fused_components), dim3(64 * waves),
+                       waves * group_bytes, st, A, pl->d_fconv, pl->d_foff, P.n_layers(), P.d, pl->d_fchains,
+                       P.fused_lanes.stride, P.fused_lanes.steps, (int)group_bytes, P.fused_simple ? 1 : 0);
+    LAUNCH_CHECK("conv_fused_kernel");
+    return record(prof, 1, st, false);
+}
+
 template <int M, bool CX>
 int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
+    if (P.fused_components > 0) return launch_fused<M, CX>(pl, A, st, prof);
     for (int L = 1; L <= P.n_layers(); ++L) {
         const long off = P.conv_off[L - 1];
         int rc = launch_layer<M, false, CX>(pl, A, pl->d_conv + off, (int)(P.conv_off[L] - off), st, prof);
@@ -500,7 +528,7 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
     if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS |
-                                MDPE_ASAP_LAYERS))
+                                MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES))
         return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
@@ -528,6 +556,9 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
         for (size_t q = 0; q < P.corr.size(); ++q) corr[q] = make_int4(P.corr[q][0], P.corr[q][1], P.corr[q][2], 0);
         std::vector<int4> scale(P.scale.size());
         for (size_t q = 0; q < P.scale.size(); ++q) scale[q] = make_int4(P.scale[q][0], P.scale[q][1], P.scale[q][2], 0);
+        std::vector<int4> fconv(P.fused_conv.size());
+        for (size_t q = 0; q < P.fused_conv.size(); ++q)
+            fconv[q] = make_int4(P.fused_conv[q][0], P.fused_conv[q][1], P.fused_conv[q][2], 0);
         std::vector<int2> add(P.add.size()), stage(P.stage.size());
         for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
         for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
@@ -542,7 +573,10 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
             (rc = upload(&raw->d_cbar, P.coeff_bar_slots.data(), P.coeff_bar_slots.size() * sizeof(int))) ||
             (rc = upload(&raw->d_zbar, P.z_bar_slots.data(), P.z_bar_slots.size() * sizeof(int))) ||
             (rc = upload(&raw->d_ybar, &P.ybar_slot, sizeof(int))) ||
-            (rc = upload(&raw->d_scale, scale.data(), scale.size() * sizeof(int4)))) {
+            (rc = upload(&raw->d_scale, scale.data(), scale.size() * sizeof(int4))) ||
+            (rc = upload(&raw->d_fconv, fconv.data(), fconv.size() * sizeof(int4))) ||
+            (rc = upload(&raw->d_foff, P.fused_off.data(), P.fused_off.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_fchains, P.fused_lanes.chains.data(), P.fused_lanes.chains.size() * sizeof(int)))) {
             std::string keep = g_err;
             free_plan(pl.release());
             g_err = keep;
@@ -570,6 +604,8 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->streamed = P.streamed ? 1 : 0;
     o->simple_dealing = P.simple ? 1 : 0;
     o->balanced_layers = P.balanced ? 1 : 0;
+    o->fused_components = P.fused_components;
+    o->fused_waves = P.fused_waves;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;
@@ -585,6 +621,23 @@ int plan_layer_sizes(const mdpe_plan *pl, int32_t *conv_sizes, int32_t *add_size
         for (int L = 0; L < P.n_layers(); ++L) conv_sizes[L] = (int32_t)(P.conv_off[L + 1] - P.conv_off[L]);
     if (add_sizes)
         for (int r = 0; r < P.n_levels(); ++r) add_sizes[r] = (int32_t)(P.add_off[r + 1] - P.add_off[r]);
+    return MDPE_OK;
+}
+
+int plan_fused_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    if (P.fused_components == 0) return fail(MDPE_EINVAL, "the plan does not fuse its layers (MDPE_FUSED_LAYERS)");
+    const int nl = P.n_layers();
+    for (int32_t c = 0; c < P.fused_components; ++c)
+        for (int L = 1; L <= nl; ++L)
+            for (int32_t q = P.fused_off[(size_t)c * (nl + 1) + L - 1]; q < P.fused_off[(size_t)c * (nl + 1) + L]; ++q) {
+                rows[5 * q] = c;
+                rows[5 * q + 1] = L;
+                rows[5 * q + 2] = P.fused_conv[q][0];
+                rows[5 * q + 3] = P.fused_conv[q][1];
+                rows[5 * q + 4] = P.fused_conv[q][2];
+            }
     return MDPE_OK;
 }
 

@@ -365,25 +365,114 @@ static bool balance_layers(Plan &P, long per_round) {
     return true;
 }
 
+// Fused layers: split the convolutions into independent components.  Two jobs
+// depend on each other only through a slot that some convolution writes (the
+// staged inputs a_k and z_i are read-only), so a union of every job's output
+// slot with each operand slot that is also written puts every read after
+// write, write after write and write after read pair in one component.  The
+// layers inside a component keep the plan's order.
+static void fuse_layers(Plan &P) {
+    const int nl = P.n_layers();
+    const size_t nj = P.conv.size();
+    if (nl < 1 || nj == 0) return;
+    std::vector<int64_t> parent(P.n_series);
+    for (int64_t s = 0; s < P.n_series; ++s) parent[s] = s;
+    auto find = [&](int64_t s) {
+        while (parent[s] != s) s = parent[s] = parent[parent[s]];
+        return s;
+    };
+    std::vector<char> written(P.n_series, 0);
+    for (const auto &t : P.conv) written[t[2]] = 1;
+    for (const auto &t : P.conv)
+        for (int o = 0; o < 2; ++o)
+            if (written[t[o]]) {
+                const int64_t a = find(t[o]), b = find(t[2]);
+                if (a != b) parent[a] = b;
+            }
+    std::vector<int32_t> comp_of_root(P.n_series, -1), comp(nj);
+    int32_t C = 0;
+    for (size_t j = 0; j < nj; ++j) {
+        const int64_t r = find(P.conv[j][2]);
+        if (comp_of_root[r] < 0) comp_of_root[r] = C++;
+        comp[j] = comp_of_root[r];
+    }
+    std::vector<int> layer(nj);
+    for (int L = 1; L <= nl; ++L)
+        for (int64_t j = P.conv_off[L - 1]; j < P.conv_off[L]; ++j) layer[j] = L;
+    // counting sort by (component, layer), stable inside each bucket
+    std::vector<int32_t> cnt((size_t)C * (nl + 1) + 1, 0);
+    for (size_t j = 0; j < nj; ++j) cnt[(size_t)comp[j] * (nl + 1) + layer[j]]++;
+    int widest = 0;
+    for (int32_t x : cnt) widest = std::max(widest, (int)x);
+    P.fused_off.assign((size_t)C * (nl + 1), 0);
+    int32_t acc = 0;
+    for (int32_t c = 0; c < C; ++c) {
+        P.fused_off[(size_t)c * (nl + 1)] = acc;
+        for (int L = 1; L <= nl; ++L) {
+            acc += cnt[(size_t)c * (nl + 1) + L];
+            P.fused_off[(size_t)c * (nl + 1) + L] = acc;
+        }
+    }
+    std::vector<int32_t> pos(P.fused_off);
+    P.fused_conv.assign(nj, {0, 0, 0});
+    for (size_t j = 0; j < nj; ++j) {
+        const size_t key = (size_t)comp[j] * (nl + 1) + layer[j] - 1;
+        P.fused_conv[pos[key]++] = P.conv[j];
+    }
+    P.fused_components = C;
+    P.fused_lanes = make_lane_schedule(P.d, 1);
+    P.fused_simple = prefer_simple_dealing(P.d, 1, P.w, P.fused_lanes.steps);
+    // up to four wavefronts (one per SIMD of a CU); the launcher lowers this
+    // where their LDS would not fit
+    P.fused_waves = std::min(4, std::max(1, widest));
+}
+
+// Fuse the layers by default where each layer is a short step that the per-layer
+// kernel boundary (~4.5 us on MI355X) would dominate: deep plans of small
+// layers (under half a round of the SIMDs), one wavefront per job, small
+// coefficients or low degree.  Measured on p2 (64 layers of 378 jobs), fused
+// against per-layer: 3.9x at one double and d = 8, 1.7x at d = 63, 1.5x at
+// two doubles and d = 63, 1.0x at four doubles and d = 63-95, 1.2x at ten
+// doubles and d = 8; slower beyond (ten doubles at d = 31: 0.95x), and
+// wherever the plan spreads a job over several wavefronts or packs many jobs
+// into one (wide layers of short series: p3 at d = 8, 0.2x).
+static bool fuse_by_default(const Plan &P) {
+    if (P.streamed || P.lanes.waves_per_job != 1 || P.n_layers() < 4) return false;
+    for (int L = 1; L <= P.n_layers(); ++L)
+        if (P.conv_off[L] - P.conv_off[L - 1] > 512) return false;
+    return P.d <= (P.w <= 4 ? 127 : 15);
+}
+
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
                        uint32_t flags, Plan &P, bool *unsupported) {
     // Staged operands unless asked otherwise, or unless they do not fit in
     // LDS, or unless streaming with several wavefronts per job is estimated
     // to be faster (large d with few jobs per layer).
     std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, P, unsupported);
-    if (!err.empty() || P.streamed || (flags & kStageOperands)) return err;
+    if (!err.empty()) return err;
+    auto fuse = [&]() {
+        if (!P.streamed && ((flags & kFusedLayers) || (!(flags & kLayerLaunches) && fuse_by_default(P))))
+            fuse_layers(P);
+        return err;
+    };
+    if (P.streamed || (flags & kStageOperands)) return fuse();
     bool paired = false;
     const int Q = stream_waves_per_job(d, &paired);
-    if (Q < 2) return err;
-    const LaneSchedule ss = paired ? make_paired_schedule(d, Q) : make_lane_schedule(d, 1, Q);
-    if (layer_cost(P, Q, 1, ss.steps, 1.2) >= layer_cost(P, 1, P.lanes.jobs_per_group, P.lanes.steps, 1.0)) return err;
-    return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, true, P, unsupported);
+    if (Q >= 2 && !(flags & kFusedLayers)) {
+        const LaneSchedule ss = paired ? make_paired_schedule(d, Q) : make_lane_schedule(d, 1, Q);
+        if (layer_cost(P, Q, 1, ss.steps, 1.2) < layer_cost(P, 1, P.lanes.jobs_per_group, P.lanes.steps, 1.0))
+            return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, true, P, unsupported);
+    }
+    return fuse();
 }
 
 static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
                                    const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported) {
     *unsupported = false;
-    if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers)) return "unknown flags";
+    if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers | kFusedLayers |
+                  kLayerLaunches))
+        return "unknown flags";
+    if ((flags & kFusedLayers) && (flags & kLayerLaunches)) return "MDPE_FUSED_LAYERS and MDPE_LAYER_LAUNCHES exclude each other";
     if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;
     const bool cx = (flags & kComplex) != 0;

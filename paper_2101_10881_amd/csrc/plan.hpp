@@ -40,6 +40,8 @@ constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then i
 constexpr uint32_t kStreamOperands = 4u;   // read both convolution operands from global memory
 constexpr uint32_t kStageOperands = 8u;    // stage them in LDS (no automatic streaming)
 constexpr uint32_t kAsapLayers = 16u;      // every convolution at its earliest layer (no balancing)
+constexpr uint32_t kFusedLayers = 32u;     // all convolution layers in one launch, per independent component
+constexpr uint32_t kLayerLaunches = 64u;   // one launch per convolution layer (no automatic fusing)
 
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
@@ -76,6 +78,19 @@ struct Plan {
     bool simple = false;
     // jobs with slack moved to later layers to fill whole rounds of the SIMDs
     bool balanced = false;
+    // fused layers (kFusedLayers, staged operands): the convolutions split into
+    // independent components (no slot written by a job of one is read or
+    // written by a job of another); fused_conv holds them by component, then
+    // layer, and component c's layer L (1-based) spans
+    // fused_conv[fused_off[c * (n_layers + 1) + L - 1] .. fused_off[c * (n_layers + 1) + L]).
+    // One workgroup of fused_waves wavefronts runs a component, one job per
+    // wavefront at a time, with the one-job lane schedule fused_lanes.
+    std::vector<std::array<int32_t, 3>> fused_conv;
+    std::vector<int32_t> fused_off;
+    int32_t fused_components = 0;
+    int32_t fused_waves = 0;
+    LaneSchedule fused_lanes;
+    bool fused_simple = false;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };

@@ -26,6 +26,9 @@ struct mdpe_plan {
     int *d_zbar = nullptr;
     int *d_ybar = nullptr;
     int4 *d_scale = nullptr;
+    int4 *d_fconv = nullptr;   // fused layers: jobs by component, then layer
+    int *d_foff = nullptr;     // fused layers: per-component layer offsets
+    int *d_fchains = nullptr;  // fused layers: the one-job lane schedule
 };
 
 namespace mdpe {

@@ -25,6 +25,8 @@ MDPE_COMPLEX = 2
 MDPE_STREAM_OPERANDS = 4
 MDPE_STAGE_OPERANDS = 8
 MDPE_ASAP_LAYERS = 16
+MDPE_FUSED_LAYERS = 32
+MDPE_LAYER_LAUNCHES = 64
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -47,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("n", ctypes.c_int32), ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64),
                 ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32),
-                ("simple_dealing", ctypes.c_int32), ("balanced_layers", ctypes.c_int32)]
+                ("simple_dealing", ctypes.c_int32), ("balanced_layers", ctypes.c_int32),
+                ("fused_components", ctypes.c_int32), ("fused_waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +97,7 @@ def lib():
     L.plan_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
     L.plan_layer_sizes.argtypes = [_vp, _i32p, _i32p]
     L.plan_conv_jobs.argtypes = [_vp, _i32p]
+    L.plan_fused_jobs.argtypes = [_vp, _i32p]
     L.plan_add_jobs.argtypes = [_vp, _i32p]
     L.plan_outputs.argtypes = [_vp, _i32p]
     L.plan_scale_jobs.argtypes = [_vp, _i32p]
@@ -210,6 +214,12 @@ class Plan:
         _check(lib().plan_conv_jobs(self._h, rows.ctypes.data_as(_i32p)))
         return rows[: self.info["n_conv"]]
 
+    def fused_jobs(self):
+        """MDPE_FUSED_LAYERS plans: rows {component, layer, t1, t2, t3} in fused launch order."""
+        rows = np.zeros((max(self.info["n_conv"], 1), 5), dtype=np.int32)
+        _check(lib().plan_fused_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[: self.info["n_conv"]]
+
     def add_jobs(self):
         rows = np.zeros((max(self.info["n_add"], 1), 3), dtype=np.int32)
         _check(lib().plan_add_jobs(self._h, rows.ctypes.data_as(_i32p)))
@@ -302,7 +312,7 @@ class Polynomial:
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
-                 stream_operands=None, asap_layers=False):
+                 stream_operands=None, asap_layers=False, fused_layers=None):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
@@ -311,7 +321,10 @@ class Polynomial:
         flags = ((MDPE_KEEP_MONOMIAL_VALUES if keep_monomials else 0) | (MDPE_COMPLEX if complex else 0) |
                  (MDPE_STREAM_OPERANDS if stream_operands is True else 0) |
                  (MDPE_STAGE_OPERANDS if stream_operands is False else 0) |
-                 (MDPE_ASAP_LAYERS if asap_layers else 0))
+                 (MDPE_ASAP_LAYERS if asap_layers else 0) |
+                 # fused_layers: None lets the plan choose, True / False forces it
+                 (MDPE_FUSED_LAYERS if fused_layers is True else 0) |
+                 (MDPE_LAYER_LAUNCHES if fused_layers is False else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)
@@ -321,9 +334,10 @@ class Polynomial:
         self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
 
     @classmethod
-    def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False):
+    def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False,
+                     fused_layers=None):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
-                   getattr(w, "exps", None), stream_operands, asap_layers)
+                   getattr(w, "exps", None), stream_operands, asap_layers, fused_layers)
 
     def new_workspace(self):
         import torch

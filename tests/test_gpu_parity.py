@@ -216,14 +216,18 @@ def test_profiled_and_side_stream(oracle_lib):
     assert_bitexact(got[1], want_g, "grad")
 
 
-def test_profiler_conv_launches_only(oracle_lib):
-    # timing only the convolution launches: the same outputs, no other events
+@pytest.mark.parametrize("fused", [False, True])
+def test_profiler_conv_launches_only(oracle_lib, fused):
+    # timing only the convolution launches (five layers, or one fused launch):
+    # the same outputs, no other events
+    import torch
     from paper_2101_10881_amd import mdpe
     w = W.random_poly("profc", 4, 33, 7, 30, [5] * 30, seed=15)
+    P = mdpe.Polynomial.for_workload(w, torch.device("cuda", 0), fused_layers=fused)
     prof = mdpe.Profiler(classes=mdpe.MDPE_TIME_CONV)
-    got = run_gpu(w, profiler=prof)
+    got = run_gpu(w, profiler=prof, poly=P)
     t = prof.read()
-    assert t["n_cnv"] == 5 and t["n_stage"] == t["n_add"] == t["n_gather"] == 0 and t["cnv_ms"] > 0
+    assert t["n_cnv"] == (1 if fused else 5) and t["n_stage"] == t["n_add"] == t["n_gather"] == 0 and t["cnv_ms"] > 0
     want_v, want_g = oracle_lib.eval_workload(w)
     assert_bitexact(got[0], want_v, "value")
     assert_bitexact(got[1], want_g, "grad")

@@ -249,7 +249,7 @@ def test_complex_plan_same_jobs_double_workspace():
 
 @pytest.mark.parametrize("flags, m, d, code", [
     (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
-    (32, 2, 3, mdpe.MDPE_EINVAL),                            # unknown flag
+    (128, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
     (mdpe.MDPE_STREAM_OPERANDS | mdpe.MDPE_STAGE_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_STAGE_OPERANDS, 10, 1700, mdpe.MDPE_EUNSUPPORTED),  # does not fit in LDS
 ])
