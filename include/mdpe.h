@@ -113,9 +113,11 @@ typedef struct {
 #define MDPE_ASAP_LAYERS 16u
 
 /* Plan flag: run every convolution layer in one launch (plans do so by
- * themselves where it is estimated faster: deep plans of layers under 512
- * jobs, one wavefront per job, d <= 127 up to four doubles per coefficient,
- * d <= 15 beyond; MDPE_LAYER_LAUNCHES keeps one launch per layer).  The jobs fall into
+ * themselves where it is estimated faster: at least four layers, one
+ * wavefront per job, at most four jobs of a component per layer, and either
+ * one double per coefficient, two up to d = 63, or layers under 512 jobs with
+ * d <= 127 up to four doubles per coefficient, d <= 15 beyond;
+ * MDPE_LAYER_LAUNCHES keeps one launch per layer).  The jobs fall into
  * independent components -- no slot written by a job of one component is read
  * or written by a job of another (for multilinear polynomials, one component
  * per monomial) -- and one workgroup runs a component's layers in order, with

@@ -371,10 +371,11 @@ static bool balance_layers(Plan &P, long per_round) {
 // slot with each operand slot that is also written puts every read after
 // write, write after write and write after read pair in one component.  The
 // layers inside a component keep the plan's order.
-static void fuse_layers(Plan &P) {
+// Returns the most jobs of one component in one layer (0 if nothing was fused).
+static int fuse_layers(Plan &P) {
     const int nl = P.n_layers();
     const size_t nj = P.conv.size();
-    if (nl < 1 || nj == 0) return;
+    if (nl < 1 || nj == 0) return 0;
     std::vector<int64_t> parent(P.n_series);
     for (int64_t s = 0; s < P.n_series; ++s) parent[s] = s;
     auto find = [&](int64_t s) {
@@ -425,19 +426,33 @@ static void fuse_layers(Plan &P) {
     // up to four wavefronts (one per SIMD of a CU); the launcher lowers this
     // where their LDS would not fit
     P.fused_waves = std::min(4, std::max(1, widest));
+    return widest;
+}
+
+static void unfuse(Plan &P) {
+    P.fused_conv.clear();
+    P.fused_off.clear();
+    P.fused_components = P.fused_waves = 0;
+    P.fused_lanes = LaneSchedule();
+    P.fused_simple = false;
 }
 
 // Fuse the layers by default where each layer is a short step that the per-layer
-// kernel boundary (~4.5 us on MI355X) would dominate: deep plans of small
-// layers (under half a round of the SIMDs), one wavefront per job, small
-// coefficients or low degree.  Measured on p2 (64 layers of 378 jobs), fused
-// against per-layer: 3.9x at one double and d = 8, 1.7x at d = 63, 1.5x at
-// two doubles and d = 63, 1.0x at four doubles and d = 63-95, 1.2x at ten
-// doubles and d = 8; slower beyond (ten doubles at d = 31: 0.95x), and
-// wherever the plan spreads a job over several wavefronts or packs many jobs
-// into one (wide layers of short series: p3 at d = 8, 0.2x).
+// kernel boundary (~4.5 us on MI355X) would dominate: deep plans, one
+// wavefront per job, and either small layers (under half a round of the
+// SIMDs) at small coefficients or low degree, or coefficients of one double
+// (two up to d = 63).  Measured, fused against per-layer: p2 (64 layers of
+// 378 jobs) 3.9x at one double and d = 8, 1.7x at d = 63, 1.5x at two doubles
+// and d = 63, 1.0x at four doubles and d = 63-95, 1.2x at ten doubles and
+// d = 8, slower beyond (ten doubles at d = 31: 0.95x); p1 (4 layers of
+// 3072-6144 jobs) 1.14-1.2x at one double, 1.12-1.13x at two up to d = 63,
+// 0.99x at d = 152, 0.87x at four doubles and d = 8.  Slower too wherever the
+// plan spreads a job over several wavefronts or packs many short jobs into one
+// (p3 at d = 8: 0.2x).  The caller also requires every component's layer to
+// fit one round of four wavefronts.
 static bool fuse_by_default(const Plan &P) {
     if (P.streamed || P.lanes.waves_per_job != 1 || P.n_layers() < 4) return false;
+    if (P.w == 1 || (P.w == 2 && P.d <= 63)) return true;
     for (int L = 1; L <= P.n_layers(); ++L)
         if (P.conv_off[L] - P.conv_off[L - 1] > 512) return false;
     return P.d <= (P.w <= 4 ? 127 : 15);
@@ -451,8 +466,11 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, P, unsupported);
     if (!err.empty()) return err;
     auto fuse = [&]() {
-        if (!P.streamed && ((flags & kFusedLayers) || (!(flags & kLayerLaunches) && fuse_by_default(P))))
+        if (P.streamed) return err;
+        if (flags & kFusedLayers)
             fuse_layers(P);
+        else if (!(flags & kLayerLaunches) && fuse_by_default(P) && fuse_layers(P) > 4)
+            unfuse(P);  // a component would need several rounds per layer
         return err;
     };
     if (P.streamed || (flags & kStageOperands)) return fuse();

@@ -105,7 +105,11 @@ def test_default_fuses_deep_plans_of_small_layers():
     assert fused(W.p2(m=1, d=8)) and fused(W.p2()) and fused(W.p2(m=4, d=95)) and fused(W.p2(m=10, d=8))
     assert not fused(W.p2(m=10, d=31))                  # long steps: the boundary no longer dominates
     assert not fused(W.p2(m=4, d=152))                  # two wavefronts per job
-    assert not fused(W.p1()) and not fused(W.p3(m=2, d=8))   # layers of thousands of jobs
+    assert not fused(W.p1()) and not fused(W.p1(m=4, d=8))   # layers of thousands of jobs
+    assert fused(W.p1(m=1, d=152)) and fused(W.p1(m=2, d=63))  # ... unless the steps are very short
+    assert not fused(W.p1(m=2, d=64)) and not fused(W.p3(m=1, d=8))  # p3: two layers
+    # the power table joins monomials into components of several jobs per layer
+    assert not fused(W.with_exponents(W.p1(m=2, d=4), 3, seed=5))
     assert not fused(W.rand3())                         # three layers
     assert not fused(W.p2(m=1, d=8), mdpe.MDPE_LAYER_LAUNCHES)
 
