@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--ms", default="1,2,3,4,5,8,10", help="sweep: precisions")
     ap.add_argument("--ds", default="0,8,15,31,63,95,127,152,159,191", help="sweep: degrees")
     ap.add_argument("--complex", action="store_true", help="sweep: complex series")
+    ap.add_argument("--layer-launches", action="store_true",
+                    help="sweep: one launch per convolution layer even where the plan would fuse them")
     ap.add_argument("--emax", type=int, default=1,
                     help="sweep: raise half of the variable occurrences to exponents 2..emax")
     ap.add_argument("--instances", type=int, default=512, help="batch: number of instances")
@@ -376,7 +378,7 @@ def run_sweep(a):
         for m in (int(x) for x in a.ms.split(",")):
             for d in (int(x) for x in a.ds.split(",")):
                 w = sweep_workload(poly, m, d, a.complex, a.emax)
-                P = mdpe.Polynomial.for_workload(w, dev)
+                P = mdpe.Polynomial.for_workload(w, dev, fused_layers=False if a.layer_launches else None)
                 coeff = torch.from_numpy(w.coeff).to(dev)
                 z = torch.from_numpy(w.z).to(dev)
                 v, g = P.eval_and_diff(coeff, z)
