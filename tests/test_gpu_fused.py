@@ -78,3 +78,19 @@ def test_fused_layers_keep_monomials_for_the_adjoint():
         out.append([t.cpu().numpy() for t in (v, g, cb, zb)])
     for a, b, what in zip(out[0], out[1], ("value", "grad", "coeff_bar", "z_bar")):
         assert_bitexact(b, a, what)
+
+
+@pytest.mark.parametrize("m,d,poly,expect", [(4, 127, "p2", True), (4, 128, "p2", False), (5, 15, "p2", True),
+                                             (5, 16, "p2", False), (2, 63, "p1", True), (2, 64, "p1", False)])
+def test_default_choice_at_its_limits(oracle_lib, m, d, poly, expect):
+    # either side of the automatic rule's degree limits, bitwise against the oracle
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = getattr(W, poly)(m=m, d=d)
+    P = mdpe.Polynomial.for_workload(w, torch.device("cuda", 0))
+    assert (P.plan.info["fused_components"] > 0) == expect
+    print(f"{w.name}: fused={expect}", flush=True)
+    got = run_gpu(w, poly=P)
+    v, g = oracle_lib.eval_workload(w)
+    assert_bitexact(got[0], v, f"{w.name} value")
+    assert_bitexact(got[1], g, f"{w.name} grad")
