@@ -287,9 +287,14 @@ __global__ __launch_bounds__(64 * WPB) void conv_layer_kernel(double *__restrict
 // wavefront without a job still meets conv_group's barrier), so the barriers
 // match.  Each job runs exactly as in conv_layer_kernel with one job per
 // group, so the output bits are those of the per-layer launches.
+// J (jobs per wavefront, 1 from the planner) is read from the argument from
+// four doubles per coefficient on and fixed at compile time below: measured
+// 5-9% faster that way at four and ten doubles (p2 4d d = 64: 2.52 -> 2.37
+// ms; 10d d = 8: 2.97 -> 2.69) and 1-4% slower at two and three, the same
+// bits -- a difference in the generated code only.
 template <int M, bool CX = false>
 __global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
-                                                          const int *__restrict__ off, int nl, int d,
+                                                          const int *__restrict__ off, int nl, int d, int J,
                                                           const int *__restrict__ chains, int stride, int steps,
                                                           int group_bytes, int simple) {
     extern __shared__ double lds[];
@@ -300,10 +305,12 @@ __global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A,
     double *mine = (double *)((char *)lds + wave * group_bytes);
     for (int L = 0; L < nl; ++L) {
         const int a = o[L], b = o[L + 1];
-        for (int r = a; r < b; r += waves) {
-            const int q = r + wave;
-            conv_group<M, false, CX, false, false>(A, jobs + (q < b ? q : a), q < b ? 1 : 0, 1, d, mine, chains,
-                                                   stride, steps, lane, lane, simple != 0);
+        const int jj = kCoef<M, CX> >= 4 ? J : 1;
+        for (int r = a; r < b; r += waves * jj) {
+            const int q = r + wave * jj;
+            const int jn = q < b ? min(jj, b - q) : 0;
+            conv_group<M, false, CX, false, false>(A, jobs + (jn > 0 ? q : a), jn, jj, d, mine, chains, stride,
+                                                   steps, lane, lane, simple != 0);
         }
         __syncthreads();
     }

@@ -347,7 +347,8 @@ int launch_layer(const mdpe_plan *pl, double *A, const int4 *jobs, int nj, hipSt
 template <int M, bool CX>
 int launch_fused(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
-    const size_t group_bytes = (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), 1) + 15) / 16 * 16;
+    const int J = P.fused_lanes.jobs_per_group;  // 1: one job per wavefront
+    const size_t group_bytes = (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
     int waves = P.fused_waves;
     while (waves > 1 && waves * group_bytes > (size_t)mdpe::kMaxLdsBytes) --waves;
     static std::atomic<bool> attr_set[kMaxDevices];
@@ -360,7 +361,7 @@ int launch_fused(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *
     int rc = record(prof, 1, st, true);
     if (rc) return rc;
     hipLaunchKernelGGL((mdpe::conv_fused_kernel<M, CX>), dim3((unsigned)P.fused_components), dim3(64 * waves),
-                       waves * group_bytes, st, A, pl->d_fconv, pl->d_foff, P.n_layers(), P.d, pl->d_fchains,
+                       waves * group_bytes, st, A, pl->d_fconv, pl->d_foff, P.n_layers(), P.d, J, pl->d_fchains,
                        P.fused_lanes.stride, P.fused_lanes.steps, (int)group_bytes, P.fused_simple ? 1 : 0);
     LAUNCH_CHECK("conv_fused_kernel");
     return record(prof, 1, st, false);
