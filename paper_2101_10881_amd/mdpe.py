@@ -309,6 +309,11 @@ class Polynomial:
     complex=True: complex series, every tensor with a leading axis of two
     (real parts, then imaginary parts), e.g. coeff [2][m][N+1][d+1].
     exps: one exponent per entry of vars_ (None: every exponent one).
+    keep_monomials: keep each monomial's product of variables for adjoint().
+    stream_operands / fused_layers: None lets the plan choose; True / False
+    forces operands read from global memory (else staged in LDS) / every
+    convolution layer in one launch (else one launch per layer).
+    asap_layers: every convolution at its earliest layer (no balancing).
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
