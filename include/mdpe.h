@@ -116,7 +116,8 @@ typedef struct {
  * themselves where it is estimated faster: at least four layers, one
  * wavefront per job, at most four jobs of a component per layer, and either
  * one double per coefficient, two up to d = 63, or layers under 512 jobs with
- * d <= 127 up to four doubles per coefficient, d <= 15 beyond;
+ * d <= 127 up to four doubles per coefficient, d <= 31 at five and ten, d <= 8
+ * at other widths;
  * MDPE_LAYER_LAUNCHES keeps one launch per layer).  The jobs fall into
  * independent components -- no slot written by a job of one component is read
  * or written by a job of another (for multilinear polynomials, one component

@@ -448,14 +448,17 @@ static void unfuse(Plan &P) {
 // 3072-6144 jobs) 1.14-1.2x at one double, 1.12-1.13x at two up to d = 63,
 // 0.99x at d = 152, 0.87x at four doubles and d = 8.  Slower too wherever the
 // plan spreads a job over several wavefronts or packs many short jobs into one
-// (p3 at d = 8: 0.2x).  The caller also requires every component's layer to
-// fit one round of four wavefronts.
+// (p3 at d = 8: 0.2x).  On p2 beyond four doubles (wall time): five doubles
+// 1.17x at d = 15, 1.0x at d = 31; ten doubles 1.14x at d = 15, 1.05x at
+// d = 31; eight doubles 1.2x at d = 8 but 0.99x at d = 15 and 0.89x at d = 31
+// (the other widths take eight doubles' limit).  The caller also requires
+// every component's layer to fit one round of four wavefronts.
 static bool fuse_by_default(const Plan &P) {
     if (P.streamed || P.lanes.waves_per_job != 1 || P.n_layers() < 4) return false;
     if (P.w == 1 || (P.w == 2 && P.d <= 63)) return true;
     for (int L = 1; L <= P.n_layers(); ++L)
         if (P.conv_off[L] - P.conv_off[L - 1] > 512) return false;
-    return P.d <= (P.w <= 4 ? 127 : 15);
+    return P.d <= (P.w <= 4 ? 127 : (P.w == 5 || P.w == 10) ? 31 : 8);
 }
 
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,

@@ -80,8 +80,9 @@ def test_fused_layers_keep_monomials_for_the_adjoint():
         assert_bitexact(b, a, what)
 
 
-@pytest.mark.parametrize("m,d,poly,expect", [(4, 127, "p2", True), (4, 128, "p2", False), (5, 15, "p2", True),
-                                             (5, 16, "p2", False), (2, 63, "p1", True), (2, 64, "p1", False)])
+@pytest.mark.parametrize("m,d,poly,expect", [(4, 127, "p2", True), (4, 128, "p2", False), (5, 31, "p2", True),
+                                             (5, 32, "p2", False), (8, 8, "p2", True), (8, 9, "p2", False),
+                                             (2, 63, "p1", True), (2, 64, "p1", False)])
 def test_default_choice_at_its_limits(oracle_lib, m, d, poly, expect):
     # either side of the automatic rule's degree limits, bitwise against the oracle
     import torch

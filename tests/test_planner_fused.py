@@ -102,8 +102,9 @@ def test_streamed_plans_do_not_fuse():
 def test_default_fuses_deep_plans_of_small_layers():
     fused = lambda w, f=0: mdpe.Plan.for_workload(w, device=-1, flags=f).info["fused_components"] > 0
     # p2: 64 layers of 378 jobs
-    assert fused(W.p2(m=1, d=8)) and fused(W.p2()) and fused(W.p2(m=4, d=95)) and fused(W.p2(m=10, d=8))
-    assert not fused(W.p2(m=10, d=31))                  # long steps: the boundary no longer dominates
+    assert fused(W.p2(m=1, d=8)) and fused(W.p2()) and fused(W.p2(m=4, d=95)) and fused(W.p2(m=10, d=31))
+    assert fused(W.p2(m=5, d=31)) and fused(W.p2(m=8, d=8))
+    assert not fused(W.p2(m=10, d=32)) and not fused(W.p2(m=8, d=9))   # the boundary no longer dominates
     assert not fused(W.p2(m=4, d=152))                  # two wavefronts per job
     assert not fused(W.p1()) and not fused(W.p1(m=4, d=8))   # layers of thousands of jobs
     assert fused(W.p1(m=1, d=152)) and fused(W.p1(m=2, d=63))  # ... unless the steps are very short
