@@ -205,6 +205,36 @@ int plan_outputs(const mdpe_plan *plan, int32_t *out_slots);
 int plan_scale_jobs(const mdpe_plan *plan, int32_t *rows);
 
 /*
+ * Check job lists against the rules a plan meets (Section 5: the jobs of one
+ * layer are independent, so they may run in any order and at once).  Host
+ * only: no device work, nothing is kept.  For callers that build or edit job
+ * lists themselves, and for testing the checker that plan_polynomial runs on
+ * every plan it builds.
+ *   n, N          variables and monomials; slots 0 .. N+n hold the staged
+ *                 inputs a_0..a_N, z_1..z_n
+ *   n_series      slots in the data array A
+ *   conv_rows     int32[n_conv][4] {layer, t1, t2, t3}, the format of
+ *                 plan_conv_jobs: layers numbered from 1, nondecreasing
+ *   add_rows      int32[n_add][3] {level, t1, t2}, the format of plan_add_jobs
+ *   out_slots     int32[1+n] (value slot, then each partial derivative's, -1
+ *                 when absent) or NULL: each must be written by some stage
+ *   extra_staged  int32[n_extra] or NULL: further slots filled at staging
+ *                 time (the derivative copies of one-variable monomials)
+ *   waves_per_job wavefronts that share one convolution job (>= 1)
+ *   streamed      nonzero when operands are read from global memory
+ * Rules: a job reads only slots written before its stage (inputs, an earlier
+ * layer, an earlier level; the convolutions all precede the additions); no two
+ * jobs of a stage write one slot; no job reads a slot another job of its stage
+ * writes; a convolution never writes its second operand, nor its first when
+ * streamed or when waves_per_job > 1; every output slot is written.
+ * Returns MDPE_OK, or MDPE_EINVAL with the first violated rule and its stage
+ * in last_error_string().
+ */
+int check_plan_jobs(int32_t n, int32_t N, int64_t n_series, const int32_t *conv_rows, int64_t n_conv,
+                    const int32_t *add_rows, int64_t n_add, const int32_t *out_slots, const int32_t *extra_staged,
+                    int64_t n_extra, int32_t waves_per_job, int32_t streamed);
+
+/*
  * Evaluate p and its gradient (Sections 4-5).
  *   coeff     device double[m][N+1][d+1], a_0 first (read only)
  *   z         device double[m][n][d+1] (read only)

@@ -772,6 +772,53 @@ int plan_reverse_jobs(const mdpe_plan *pl, int32_t *rows) {
     return MDPE_OK;
 }
 
+int check_plan_jobs(int32_t n, int32_t N, int64_t n_series, const int32_t *conv_rows, int64_t n_conv,
+                    const int32_t *add_rows, int64_t n_add, const int32_t *out_slots, const int32_t *extra_staged,
+                    int64_t n_extra, int32_t waves_per_job, int32_t streamed) {
+    if (n < 1 || N < 0 || n_series < 1 + (int64_t)N + n || n_series > INT32_MAX)
+        return fail(MDPE_EINVAL, "need n >= 1, N >= 0 and 1 + N + n <= n_series < 2^31");
+    if (n_conv < 0 || n_add < 0 || n_extra < 0 || waves_per_job < 1)
+        return fail(MDPE_EINVAL, "negative count, or waves_per_job < 1");
+    if ((n_conv && !conv_rows) || (n_add && !add_rows) || (n_extra && !extra_staged))
+        return fail(MDPE_EINVAL, "NULL rows");
+    mdpe::Plan P;
+    P.n = n;
+    P.N = N;
+    P.n_series = n_series;
+    P.streamed = streamed != 0;
+    P.lanes.waves_per_job = waves_per_job;
+    for (int32_t s = 0; s < 1 + N + n; ++s) P.stage.push_back({s, s});
+    for (int64_t q = 0; q < n_extra; ++q) {
+        if (extra_staged[q] < 0 || extra_staged[q] >= n_series) return fail(MDPE_EINVAL, "staged slot out of range");
+        P.stage.push_back({extra_staged[q], 0});
+    }
+    // rows grouped by layer / level, numbered from 1 in nondecreasing order
+    // off[L-1] .. off[L]: the rows of layer (level) L
+    auto group = [&](const int32_t *rows, int64_t count, int width, std::vector<int64_t> &off) -> bool {
+        off.assign(1, 0);
+        int32_t cur = 1;
+        for (int64_t q = 0; q < count; ++q) {
+            const int32_t L = rows[width * q];
+            if (L < cur) return false;
+            for (; cur < L; ++cur) off.push_back(q);
+        }
+        if (count > 0) off.push_back(count);
+        return true;
+    };
+    if (!group(conv_rows, n_conv, 4, P.conv_off)) return fail(MDPE_EINVAL, "conv rows: layers must start at 1 and not decrease");
+    if (!group(add_rows, n_add, 3, P.add_off)) return fail(MDPE_EINVAL, "add rows: levels must start at 1 and not decrease");
+    for (int64_t q = 0; q < n_conv; ++q) P.conv.push_back({conv_rows[4 * q + 1], conv_rows[4 * q + 2], conv_rows[4 * q + 3]});
+    for (int64_t q = 0; q < n_add; ++q) P.add.push_back({add_rows[3 * q + 1], add_rows[3 * q + 2]});
+    if (out_slots)
+        for (int32_t o = 0; o <= n; ++o) {
+            if (out_slots[o] < -1 || out_slots[o] >= n_series) return fail(MDPE_EINVAL, "output slot out of range");
+            P.out_slots.push_back(out_slots[o]);
+        }
+    std::string e = mdpe::check_hazards(P);
+    if (!e.empty()) return fail(MDPE_EINVAL, e);
+    return MDPE_OK;
+}
+
 void plan_destroy(mdpe_plan *pl) { free_plan(pl); }
 
 const char *last_error_string(void) { return g_err.c_str(); }

@@ -165,7 +165,7 @@ static int tree_rounds(std::vector<int32_t> live, std::vector<std::vector<std::a
     return live.empty() ? -1 : live[0];
 }
 
-static std::string check_hazards(const Plan &P) {
+std::string check_hazards(const Plan &P) {
     // Each slot's last writer stage: inputs at stage 0, conv layer L at stage
     // L, addition level r at stage n_layers + r.  A job may read a slot only
     // when it was written at an earlier stage, and two jobs of one stage may
@@ -181,7 +181,11 @@ static std::string check_hazards(const Plan &P) {
             // written, so it may never be the job's own output
             const bool conv_stage = stage <= P.n_layers() || stage > P.n_layers() + 1 + P.n_levels();
             if (conv_stage && jobs[q][1] == w) return "second operand is the output";
-            if (conv_stage && P.streamed && jobs[q][0] == w) return "first operand is the output (streamed)";
+            // nor the first one when it is streamed, or when a job spans several
+            // wavefronts (each stages it on its own, not necessarily before
+            // another wavefront of the job stores)
+            if (conv_stage && (P.streamed || P.lanes.waves_per_job > 1) && jobs[q][0] == w)
+                return "first operand is the output (streamed, or a job over several wavefronts)";
             if (w < 0 || w >= P.n_series) return "slot out of range";
             if (!writer.emplace(w, (int)q).second) return "two jobs write one slot";
         }
@@ -189,9 +193,9 @@ static std::string check_hazards(const Plan &P) {
             for (int r = 0; r < 2; ++r) {
                 int32_t s = jobs[q][r];
                 if (s < 0 || s >= P.n_series) return "slot out of range";
-                if (written[s] < 0 || written[s] >= stage) return "read before write";
                 auto it = writer.find(s);
                 if (it != writer.end() && it->second != (int)q) return "read of a slot written in the same stage";
+                if (written[s] < 0 || written[s] >= stage) return "read before write";
             }
         for (auto &j : jobs) written[j[2]] = stage;
         return "";
@@ -229,7 +233,8 @@ static std::string check_hazards(const Plan &P) {
 }
 
 static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
-                                   const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported);
+                                   const int32_t *exps, uint32_t flags, bool stream, bool no_inplace, Plan &P,
+                                   bool *unsupported);
 
 // Relative cost of a layer plan: each layer takes about ceil(wavefronts /
 // SIMDs) wavefront lifetimes (a SIMD's throughput hardly depends on how many
@@ -466,7 +471,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     // Staged operands unless asked otherwise, or unless they do not fit in
     // LDS, or unless streaming with several wavefronts per job is estimated
     // to be faster (large d with few jobs per layer).
-    std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, P, unsupported);
+    std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, false, P, unsupported);
     if (!err.empty()) return err;
     auto fuse = [&]() {
         if (P.streamed) return err;
@@ -482,13 +487,14 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     if (Q >= 2 && !(flags & kFusedLayers)) {
         const LaneSchedule ss = paired ? make_paired_schedule(d, Q) : make_lane_schedule(d, 1, Q);
         if (layer_cost(P, Q, 1, ss.steps, 1.2) < layer_cost(P, 1, P.lanes.jobs_per_group, P.lanes.steps, 1.0))
-            return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, true, P, unsupported);
+            return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, true, false, P, unsupported);
     }
     return fuse();
 }
 
 static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
-                                   const int32_t *exps, uint32_t flags, bool stream, Plan &P, bool *unsupported) {
+                                   const int32_t *exps, uint32_t flags, bool stream, bool no_inplace, Plan &P,
+                                   bool *unsupported) {
     *unsupported = false;
     if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers | kFusedLayers |
                   kLayerLaunches))
@@ -559,7 +565,11 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
     // Streamed operands when a job's LDS operands would not fit in one
     // workgroup's LDS, or when asked for.  Then no convolution may write its
     // own first operand: b_{n-2} * a and every common-factor step after the
-    // first get fresh output slots, after all others.
+    // first get fresh output slots, after all others.  The same holds for
+    // staged operands when one job is spread over several wavefronts
+    // (no_inplace): each wavefront stages the first operand on its own, and
+    // the wavefronts of a job need not share a workgroup, so one of them could
+    // store output coefficients before another has read them.
     const bool fits = (long)(d + 1) * lds_doubles_per_coef(w) * 8 <= kMaxLdsBytes - 32768;
     if ((flags & kStageOperands) && !fits) {
         *unsupported = true;
@@ -567,6 +577,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
                "((d+1)*w*8 <= 131072 bytes, w = m doubles per coefficient, 2m complex; twice that when w <= 2)";
     }
     const bool streamed = stream || (flags & kStreamOperands) || !fits;
+    const bool fresh_out = streamed || no_inplace;
     int64_t n3 = 0, nfac_extra = 0;
     for (int k = 0, q = 0; k < N; q += nvars[k], ++k) {
         n3 += nvars[k] >= 3;
@@ -575,7 +586,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         nfac_extra += std::max(0, cnt - 1);
     }
     const int64_t xbase = mbase + (keep ? nmono2 + 1 + N + n : 0);
-    const int64_t nser = xbase + (streamed ? n3 + nfac_extra : 0);
+    const int64_t nser = xbase + (fresh_out ? n3 + nfac_extra : 0);
     if (nser > INT32_MAX / 2) {
         *unsupported = true;
         return "too many series for 32-bit slot indices";
@@ -624,7 +635,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         int shift = 0;
         for (int j = 0; e && j < nk; ++j) {
             if (e[j] < 2) continue;
-            const int32_t fac = streamed && a_slot != (int32_t)(k + 1) ? fresh() : (int32_t)(fbase + fpos);
+            const int32_t fac = fresh_out && a_slot != (int32_t)(k + 1) ? fresh() : (int32_t)(fbase + fpos);
             const int ready = e[j] - 1 >= 2 ? e[j] - 2 : 0;
             shift = std::max(shift, ready) + 1;
             add_job(shift, a_slot, pow_slot(v[j], e[j] - 1), fac);
@@ -667,7 +678,8 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
                 job(1, Z(nk), Z(nk - 1), B(1));
                 for (int j = 2; j <= nk - 2; ++j) job(j, B(j - 1), Z(nk - j), B(j));
                 // b_{n-2} := b_{n-2} * a_k, in place unless operands are streamed
-                const int32_t bfin = streamed ? fresh() : B(nk - 2);
+                // or a job spans several wavefronts
+                const int32_t bfin = fresh_out ? fresh() : B(nk - 2);
                 if (keep) {
                     // M_k = b_{n-2} * z_{i_1} reads the backward product before its
                     // multiplication by a_k, which therefore moves one layer later
@@ -728,9 +740,6 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         }
     }
 
-    auto err = check_hazards(P);
-    if (!err.empty()) return "internal planner error: " + err;
-
     if (xpos != nser - xbase) return "internal planner error: fresh slot count";
     if (streamed) {
         bool paired = false;
@@ -787,7 +796,18 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         // layers, such as p2, at one or two doubles per coefficient)
         for (int Q = 2; Q <= 4 && w <= 2 && d + 1 > (Q - 1) * kLanes; ++Q)
             consider(make_lane_schedule(d, 1, Q), true, layer_cost(P, Q, 1, dealt_steps(d, 1, Q), w == 1 ? 0.15 : 0.4));
+        // A job over several wavefronts may not write its own first operand
+        // (see no_inplace above): rebuild with fresh output slots for the
+        // in-place jobs.  The jobs and layers are the same, so is the choice.
+        if (P.lanes.waves_per_job > 1 && !no_inplace) {
+            bool inplace = false;
+            for (const auto &t : P.conv) inplace |= t[0] == t[2];
+            if (inplace) return build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, true, P, unsupported);
+        }
     }
+    // after the lane choice: the check depends on the wavefronts per job
+    auto err = check_hazards(P);
+    if (!err.empty()) return "internal planner error: " + err;
     if (!(flags & kAsapLayers)) {
         const int J = P.lanes.jobs_per_group, Q = P.lanes.waves_per_job;
         const double before = layer_cost(P, Q, J, P.lanes.steps, 1.0);

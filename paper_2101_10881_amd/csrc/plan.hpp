@@ -113,5 +113,13 @@ bool prefer_simple_dealing(int d, int J, int w, int schedule_steps);
 // turn (the slowest wavefront's).
 int dealt_steps(int d, int J, int Q = 1);
 int choose_jobs_per_group(int d, int w);
+// The rules every plan meets (Section 5: the jobs of one layer are
+// independent): a job reads only slots written at an earlier stage (inputs,
+// an earlier layer or level); no two jobs of a stage write one slot, and no
+// job reads a slot another job of its stage writes; a convolution never
+// writes its second operand, nor its first when operands are streamed or a
+// job spans several wavefronts; output slots are written.  Returns "" or
+// what is violated, naming the stage.
+std::string check_hazards(const Plan &P);
 
 }  // namespace mdpe

@@ -112,6 +112,8 @@ def lib():
     L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.eval_adjoint_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.plan_reverse_jobs.argtypes = [_vp, _i32p]
+    L.check_plan_jobs.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i32p, ctypes.c_int64, _i32p,
+                                  ctypes.c_int64, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
     L.plan_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(BatchTile), ctypes.c_int,
                              ctypes.POINTER(_vp)]
     L.batch_info.argtypes = [_vp, ctypes.POINTER(BatchInfo)]
@@ -234,6 +236,24 @@ class Plan:
         rows = np.zeros((max(self.info["n_scale"], 1), 3), dtype=np.int32)
         _check(lib().plan_scale_jobs(self._h, rows.ctypes.data_as(_i32p)))
         return rows[: self.info["n_scale"]]
+
+
+def check_plan_jobs(n, N, n_series, conv_rows, add_rows, out_slots=None, extra_staged=None, waves_per_job=1,
+                    streamed=False):
+    """Host-only check of job rows ({layer, t1, t2, t3} and {level, t1, t2}, as
+    Plan.conv_jobs / Plan.add_jobs return them); raises MdpeError naming the
+    violated rule."""
+    conv = np.ascontiguousarray(np.asarray(conv_rows, dtype=np.int32).reshape(-1, 4))
+    add = np.ascontiguousarray(np.asarray(add_rows, dtype=np.int32).reshape(-1, 3))
+    out = None if out_slots is None else np.ascontiguousarray(out_slots, dtype=np.int32)
+    if out is not None and out.shape != (int(n) + 1,):
+        raise ValueError("out_slots must have 1 + n entries")
+    extra = np.ascontiguousarray(np.zeros(0) if extra_staged is None else extra_staged, dtype=np.int32)
+    _check(lib().check_plan_jobs(int(n), int(N), int(n_series), conv.ctypes.data_as(_i32p), int(conv.shape[0]),
+                                 add.ctypes.data_as(_i32p), int(add.shape[0]),
+                                 out.ctypes.data_as(_i32p) if out is not None else None,
+                                 extra.ctypes.data_as(_i32p) if extra.size else None, int(extra.size),
+                                 int(waves_per_job), int(bool(streamed))))
 
 
 def plan_polynomial(n, nvars, vars_, d, m, device=0) -> Plan:
