@@ -263,14 +263,17 @@ int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, d
  * N + (present variables) correlation jobs on the convolution kernel.
  *   ybar      device double[m][d+1] (read only)
  *   workspace the buffer of the preceding eval_and_diff with this plan, on
- *             the same stream, unmodified since
+ *             the same stream, unmodified since: it holds the monomial
+ *             products M_k (the pass writes its own slots of it)
+ *   grad      device double[m][n][d+1] (read only): the gradient g that
+ *             eval_and_diff returned, copied into the workspace first
  *   coeff_bar device double[m][N+1][d+1] (written)
  *   z_bar     device double[m][n][d+1] (written; absent variables get +0.0)
  * The adjoint of an m-double is returned as an m-double: limb 0 is the
  * double-precision value of the derivative and the lower limbs extend it.
  */
-int eval_adjoint(const mdpe_plan *plan, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
-                 void *stream);
+int eval_adjoint(const mdpe_plan *plan, const double *ybar, void *workspace, const double *grad, double *coeff_bar,
+                 double *z_bar, void *stream);
 
 /* Reverse-pass jobs as rows {t1 (ybar slot), t2 (M_k or gradient slot), t3}. */
 int plan_reverse_jobs(const mdpe_plan *plan, int32_t *rows);
@@ -289,8 +292,8 @@ int profiler_create(mdpe_profiler **out);
 int eval_and_diff_profiled(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
                            double *grad, void *workspace, void *stream, mdpe_profiler *prof);
 /* Same as eval_adjoint, timed (correlation launches count as convolution). */
-int eval_adjoint_profiled(const mdpe_plan *plan, const double *ybar, void *workspace, double *coeff_bar,
-                          double *z_bar, void *stream, mdpe_profiler *prof);
+int eval_adjoint_profiled(const mdpe_plan *plan, const double *ybar, void *workspace, const double *grad,
+                          double *coeff_bar, double *z_bar, void *stream, mdpe_profiler *prof);
 /* Which launches get an event pair: a mask of MDPE_TIME_STAGE, MDPE_TIME_CONV,
  * MDPE_TIME_ADD and MDPE_TIME_GATHER (all by default).  Each pair is two more
  * commands on the stream (~0.12 ms per p1 evaluation for all 17 launches), so
@@ -346,11 +349,42 @@ typedef struct {
     int64_t lds_bytes;
     int32_t grid;               /* persistent workgroups (known after the first launch) */
     int32_t m1, m2;
+    int64_t workspace_bytes;    /* the one workspace eval_and_diff_batch needs: every
+                                   instance's plan_info().workspace_bytes, each part
+                                   rounded up to 256 bytes */
 } mdpe_batch_info;
 
-/* plans[count]: device plans on one device.  tiles may be NULL (ntiles = 0). */
-int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
-               mdpe_batch **out);
+/* Plan the batch once (Section 5 builds the job lists once and evaluates them
+ * per call; the batch does the same for all its instances).
+ *   plans      [count] device plans on one device, which must outlive the batch
+ *   tune_cache path of the autotuner's JSON cache, or NULL / "" for the
+ *              default tiles.  The tiles listed under the device's
+ *              architecture name ("gfx950") are used; a cache without that
+ *              name gives the defaults.  MDPE_EINVAL when the file cannot be
+ *              read or is not such a cache.  The file is read during the call
+ *              only. */
+int plan_batch(const mdpe_plan *const *plans, int count, const char *tune_cache, mdpe_batch **out);
+/* The same with the tiles given directly: tiles may be NULL (ntiles = 0). */
+int plan_batch_tiles(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
+                     mdpe_batch **out);
+/*
+ * Evaluate every instance and its gradient in one persistent launch, replayed
+ * from a hipGraph captured at the first call (the hot path of the batch).
+ *   coeff, z, value, grad  host arrays [count] of device pointers, each with
+ *             the meaning and layout of eval_and_diff for that instance
+ *   workspace one device buffer of batch_info().workspace_bytes, 256-byte
+ *             aligned; instance p uses its own part of it
+ *   stream    hipStream_t or NULL
+ * Stream-ordered and without host synchronisation: when a pointer differs
+ * from the previous call's, the new pointer table is copied to the device on
+ * `stream` (through one of four pinned host buffers; only a caller more than
+ * four rebinds ahead of the device waits for the oldest copy), then the graph
+ * is replayed on `stream`.  Bits are those of eval_and_diff per instance.
+ * Calls (and batch_launch* calls) on different streams must not overlap: they
+ * share the batch's pointer table and counters.
+ */
+int eval_and_diff_batch(mdpe_batch *batch, const double *const *coeff, const double *const *z,
+                        double *const *value, double *const *grad, void *workspace, void *stream);
 int batch_info(const mdpe_batch *batch, mdpe_batch_info *out);
 /* rows int32[n_tasks][6]: {instance, kind (0 stage, 1 conv, 2 add, 3 gather),
  * counter threshold, count, first, queue (XCD)}, queues concatenated, each in

@@ -534,42 +534,6 @@ int oracle_eval_and_diff(int m, int d, int n, int N, const int *nvars, const int
     return oracle_eval_and_diff_general(m, 0, d, n, N, nvars, vars, NULL, coeff, z, value, grad, nthreads);
 }
 
-/*
- * One monomial's raw products, for sampled checks at sizes where the whole
- * oracle is too slow: out receives the value series and the nk partial
- * derivative series of monomial a * prod z_{v[j]}, planar [m][nk+1][d+1]
- * (value first, then d/dz_{v[0]}, ...).
- */
-int oracle_monomial(int m, int d, int n, int nk, const int *v, const double *a /* [m][d+1] */,
-                    const double *z /* [m][n][d+1] */, double *out)
-{
-    if (m < 1 || m > MAXM || d < 0 || nk < 1 || nk > n)
-        return -1;
-    for (int j = 0; j < nk; ++j)
-        if (v[j] < 0 || v[j] >= n || (j > 0 && v[j] <= v[j - 1]))
-            return -1;
-    const size_t S = (size_t)(d + 1) * m;
-    double *A = (double *)malloc(sizeof(double) * S);
-    double *Z = (double *)malloc(sizeof(double) * S * (size_t)n);
-    double *res = (double *)malloc(sizeof(double) * S * (size_t)(nk + 1));
-    double *work = (double *)malloc(sizeof(double) * S * (size_t)(3 * nk + 1));
-    double **der = (double **)malloc(sizeof(double *) * (size_t)nk);
-    from_planar(m, d, 1, a, A);
-    from_planar(m, d, n, z, Z);
-    for (int j = 0; j < nk; ++j)
-        der[j] = res + (size_t)(j + 1) * S;
-    monomial(m, 0, d, nk, v, A, Z, res, der, work, work + S * (size_t)nk, work + 2 * S * (size_t)nk,
-             work + 3 * S * (size_t)nk);
-    for (int j = 0; j <= nk; ++j)
-        to_planar(m, d, nk + 1, j, res + (size_t)j * S, out);
-    free(A);
-    free(Z);
-    free(res);
-    free(work);
-    free(der);
-    return 0;
-}
-
 /* --------------------------------------------------------- the adjoint -- */
 /*
  * Reverse pass for an upstream adjoint series ybar of the value series:
@@ -698,25 +662,6 @@ int oracle_md_op(int op, int m, long count, const double *x, const double *y, do
         for (int l = 0; l < w; ++l)
             z[(size_t)l * count + i] = r[l];
     }
-    return 0;
-}
-
-/* z = x * y truncated at degree d; planar [m][d+1]. */
-int oracle_conv(int m, int d, const double *x, const double *y, double *z)
-{
-    if (m < 1 || m > MAXM || d < 0)
-        return -1;
-    const size_t S = (size_t)(d + 1) * m;
-    double *X = (double *)malloc(sizeof(double) * S), *Y = (double *)malloc(sizeof(double) * S);
-    double *Zs = (double *)malloc(sizeof(double) * S), *T = (double *)malloc(sizeof(double) * S);
-    from_planar(m, d, 1, x, X);
-    from_planar(m, d, 1, y, Y);
-    conv(m, 0, d, X, Y, Zs, T);
-    to_planar(m, d, 1, 0, Zs, z);
-    free(X);
-    free(Y);
-    free(Zs);
-    free(T);
     return 0;
 }
 

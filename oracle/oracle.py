@@ -25,9 +25,7 @@ def bind(path):
     L = ctypes.CDLL(path)
     L.oracle_eval_and_diff.argtypes = [ctypes.c_int] * 4 + [_ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
     L.oracle_eval_and_diff_general.argtypes = [ctypes.c_int] * 5 + [_ip, _ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_int]
-    L.oracle_monomial.argtypes = [ctypes.c_int] * 4 + [_ip, _dp, _dp, _dp]
     L.oracle_md_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
-    L.oracle_conv.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     L.oracle_eft.argtypes = [ctypes.c_int, ctypes.c_long, _dp, _dp, _dp, _dp]
     L.oracle_op_counts.argtypes = [ctypes.c_int, ctypes.c_int, _lp]
     L.oracle_tree_schedule.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int]
@@ -91,18 +89,6 @@ def eval_workload(w, nthreads=0, L=None):
     return eval_and_diff(w.m, w.d, w.n, w.nvars, w.vars, w.coeff, w.z, nthreads, L, getattr(w, "exps", None))
 
 
-def monomial(m, d, n, v, a, z):
-    """Value and partials of a * prod z_v as [m][nk+1][d+1] (value first)."""
-    v = _i32(v)
-    nk = int(v.shape[0])
-    a, z = _f64(a), _f64(z)
-    assert a.shape == (m, d + 1) and z.shape == (m, n, d + 1)
-    out = np.empty((m, nk + 1, d + 1))
-    if lib().oracle_monomial(m, d, n, nk, _i(v), _d(a), _d(z), _d(out)) != 0:
-        raise ValueError("oracle: invalid monomial")
-    return out
-
-
 def md_op(op, x, y, L=None):
     """op 'add' or 'mul' on planar [m][count] arrays; 'cadd' or 'cmul' on
     complex [2][m][count] arrays."""
@@ -113,16 +99,6 @@ def md_op(op, x, y, L=None):
     z = np.empty_like(x)
     if (L or lib()).oracle_md_op(code, m, count, _d(x), _d(y), _d(z)) != 0:
         raise ValueError("oracle: bad md op")
-    return z
-
-
-def conv(x, y):
-    """Truncated product of two series, planar [m][d+1]."""
-    x, y = _f64(x), _f64(y)
-    m, d1 = x.shape
-    z = np.empty_like(x)
-    if lib().oracle_conv(m, d1 - 1, _d(x), _d(y), _d(z)) != 0:
-        raise ValueError("oracle: bad conv")
     return z
 
 

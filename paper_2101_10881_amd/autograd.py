@@ -30,13 +30,15 @@ class PolyEvalFunction(torch.autograd.Function):
         ctx.poly = poly
         ctx.ws = ws
         ctx.mark_non_differentiable(grad)
+        ctx.save_for_backward(grad)
         return value, grad
 
     @staticmethod
     def backward(ctx, ybar, _grad_bar):
         if ybar is None:
             return None, None, None
-        cbar, zbar = ctx.poly.adjoint(ybar.contiguous(), workspace=ctx.ws)
+        (grad,) = ctx.saved_tensors
+        cbar, zbar = ctx.poly.adjoint(ybar.contiguous(), grad, workspace=ctx.ws)
         return cbar, zbar, None
 
 

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -201,6 +202,16 @@ struct mdpe_batch {
     hipGraph_t graph = nullptr;
     hipStream_t cap = nullptr;
     std::vector<int> stage_tasks;  // tasks per kind, for batch_info
+    // eval_and_diff_batch: instance p's workspace starts ws_off[p] bytes into
+    // the caller's one workspace of ws_bytes; pointer tables are staged in a
+    // ring of pinned host buffers, each reused once its copy has run
+    std::vector<int64_t> ws_off;
+    int64_t ws_bytes = 0;
+    static constexpr int kRing = 4;
+    mdpe::BatchInst *ring[kRing] = {};
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_used[kRing] = {};
+    int ring_next = 0;
 };
 
 namespace {
@@ -217,6 +228,13 @@ void free_batch(mdpe_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int r = 0; r < mdpe_batch::kRing; ++r) {
+        if (b->ring_ev[r]) {
+            (void)hipEventSynchronize(b->ring_ev[r]);
+            (void)hipEventDestroy(b->ring_ev[r]);
+        }
+        if (b->ring[r]) (void)hipHostFree(b->ring[r]);
+    }
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_tasks);
     (void)hipFree(b->d_qinfo);
@@ -277,12 +295,201 @@ int launch_any(mdpe_batch *b, hipStream_t st, bool prepare_only = false) {
     return bfail(MDPE_EUNSUPPORTED, "batch precisions must be all equal, or {2, 4}");
 }
 
+// ------------------------------------------------------- the tune cache --
+// The autotuner writes JSON: {"<arch>": {"tiles": [{"m": .., "d": ..,
+// "jobs_per_group": .., "groups_per_task": .., "add_items_per_task": ..}, ...],
+// other keys ...}, ...}.  A small reader for exactly that much JSON.
+struct JVal {
+    enum Kind { kNull, kBool, kNum, kStr, kArr, kObj } kind = kNull;
+    double num = 0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::vector<std::pair<std::string, JVal>> obj;
+    const JVal *get(const std::string &k) const {
+        for (auto &kv : obj)
+            if (kv.first == k) return &kv.second;
+        return nullptr;
+    }
+};
+
+struct JReader {
+    const char *p, *e;
+    void ws() {
+        while (p < e && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+    }
+    bool lit(const char *w) {
+        const size_t n = std::strlen(w);
+        if ((size_t)(e - p) < n || std::strncmp(p, w, n) != 0) return false;
+        p += n;
+        return true;
+    }
+    bool string(std::string &out) {
+        if (p >= e || *p != '"') return false;
+        for (++p; p < e && *p != '"'; ++p) {
+            if (*p == '\\') {
+                if (++p >= e) return false;
+                out.push_back(*p == 'n' ? '\n' : *p == 't' ? '\t' : *p);  // \uXXXX is not expected in a tune cache
+            } else {
+                out.push_back(*p);
+            }
+        }
+        if (p >= e) return false;
+        ++p;
+        return true;
+    }
+    bool value(JVal &v, int depth) {
+        if (depth > 32) return false;
+        ws();
+        if (p >= e) return false;
+        if (*p == '{') {
+            v.kind = JVal::kObj;
+            ++p;
+            ws();
+            if (p < e && *p == '}') return ++p, true;
+            for (;;) {
+                ws();
+                std::string k;
+                if (!string(k)) return false;
+                ws();
+                if (p >= e || *p++ != ':') return false;
+                JVal x;
+                if (!value(x, depth + 1)) return false;
+                v.obj.emplace_back(std::move(k), std::move(x));
+                ws();
+                if (p < e && *p == ',') { ++p; continue; }
+                if (p < e && *p == '}') return ++p, true;
+                return false;
+            }
+        }
+        if (*p == '[') {
+            v.kind = JVal::kArr;
+            ++p;
+            ws();
+            if (p < e && *p == ']') return ++p, true;
+            for (;;) {
+                JVal x;
+                if (!value(x, depth + 1)) return false;
+                v.arr.push_back(std::move(x));
+                ws();
+                if (p < e && *p == ',') { ++p; continue; }
+                if (p < e && *p == ']') return ++p, true;
+                return false;
+            }
+        }
+        if (*p == '"') {
+            v.kind = JVal::kStr;
+            return string(v.str);
+        }
+        if (lit("true") || lit("false")) return v.kind = JVal::kBool, true;
+        if (lit("null")) return true;
+        char *end = nullptr;
+        std::string num(p, (size_t)std::min<ptrdiff_t>(e - p, 64));
+        v.num = std::strtod(num.c_str(), &end);
+        if (end == num.c_str()) return false;
+        v.kind = JVal::kNum;
+        p += end - num.c_str();
+        return true;
+    }
+};
+
+// Tiles for `arch` from the cache file at `path`; an absent arch key gives
+// no tiles (the defaults).  Returns "" or an error message.
+std::string read_tune_cache(const char *path, const std::string &arch, std::vector<mdpe_batch_tile> &tiles) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return std::string("cannot read the tune cache ") + path;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) {
+        text.append(buf, got);
+        if (text.size() > (16u << 20)) break;
+    }
+    std::fclose(f);
+    JVal root;
+    JReader r{text.data(), text.data() + text.size()};
+    if (!r.value(root, 0) || root.kind != JVal::kObj) return std::string("tune cache ") + path + ": not a JSON object";
+    const JVal *dev = root.get(arch);
+    if (!dev) return "";
+    const JVal *list = dev->kind == JVal::kObj ? dev->get("tiles") : nullptr;
+    if (!list || list->kind != JVal::kArr) return std::string("tune cache ") + path + ": no tile list for " + arch;
+    for (const JVal &t : list->arr) {
+        auto field = [&](const char *k, bool need, int32_t &out) {
+            const JVal *x = t.kind == JVal::kObj ? t.get(k) : nullptr;
+            if (!x) return !need;
+            if (x->kind != JVal::kNum || x->num < 0 || x->num > 1e9 || x->num != (double)(int64_t)x->num) return false;
+            out = (int32_t)x->num;
+            return true;
+        };
+        mdpe_batch_tile tile{0, 0, 0, 0, 0};
+        if (!field("m", true, tile.m) || !field("d", true, tile.d) || !field("jobs_per_group", false, tile.jobs_per_group) ||
+            !field("groups_per_task", false, tile.groups_per_task) ||
+            !field("add_items_per_task", false, tile.add_items_per_task))
+            return std::string("tune cache ") + path + ": a tile needs integer m, d and tile fields";
+        tiles.push_back(tile);
+    }
+    return "";
+}
+
+// the device's architecture name without feature suffixes ("gfx950")
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (device < 0 || hipGetDeviceProperties(&prop, device) != hipSuccess) return "gfx950";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// capture [reset, persistent kernel] once on a private stream, replay on `stream`
+int launch_graph_on(mdpe_batch *b, hipStream_t stream) {
+    int rc = MDPE_OK;
+    if (!b->exec) {
+        if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        rc = launch_any(b, b->cap, true);  // attributes and grid, outside the capture
+        if (!rc) {
+            BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            rc = launch_any(b, b->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap, &g);
+            if (!rc && e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            if (!rc) {
+                b->graph = g;
+                e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+    }
+    if (!rc) {
+        hipError_t e = hipGraphLaunch(b->exec, stream);
+        if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
 
-int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
-               mdpe_batch **out) {
+int plan_batch(const mdpe_plan *const *plans, int count, const char *tune_cache, mdpe_batch **out) {
+    if (!plans || !out || count <= 0) return bfail(MDPE_EINVAL, "plans, count > 0 and out are required");
+    *out = nullptr;
+    std::vector<mdpe_batch_tile> tiles;
+    if (tune_cache && *tune_cache) {
+        if (!plans[0]) return bfail(MDPE_EINVAL, "NULL plan in the batch");
+        std::string err;
+        try {
+            err = read_tune_cache(tune_cache, device_arch(plans[0]->device), tiles);
+        } catch (const std::bad_alloc &) {
+            return bfail(MDPE_ENOMEM, "host allocation failed while reading the tune cache");
+        }
+        if (!err.empty()) return bfail(MDPE_EINVAL, err);
+    }
+    return plan_batch_tiles(plans, count, tiles.data(), (int)tiles.size(), out);
+}
+
+int plan_batch_tiles(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *tiles, int ntiles,
+                     mdpe_batch **out) {
     if (!plans || !out || count <= 0) return bfail(MDPE_EINVAL, "plans, count > 0 and out are required");
     if (ntiles < 0 || (ntiles > 0 && !tiles)) return bfail(MDPE_EINVAL, "bad tiles");
     *out = nullptr;
@@ -361,6 +568,14 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
     }
     std::vector<Tmp> tmp;
     B->insts.resize(count);
+    // one workspace for all instances: each instance's part 256-byte aligned
+    B->ws_off.resize(count);
+    for (int p = 0; p < count; ++p) {
+        const mdpe::Plan &P = plans[p]->P;
+        B->ws_off[p] = B->ws_bytes;
+        const int64_t bytes = P.n_series * (int64_t)(P.d + 1) * P.w * (int64_t)sizeof(double);
+        B->ws_bytes += (bytes + 255) / 256 * 256;
+    }
     size_t lds = 0;
     for (int p = 0; p < count; ++p) {
         const mdpe::Plan &P = plans[p]->P;
@@ -475,6 +690,11 @@ int plan_batch(const mdpe_plan *const *plans, int count, const mdpe_batch_tile *
                 if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
             }
     }
+    for (int r = 0; !rc && r < mdpe_batch::kRing; ++r) {
+        hipError_t e = hipHostMalloc((void **)&B->ring[r], sizeof(mdpe::BatchInst) * (size_t)count, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ring_ev[r], hipEventDisableTiming);
+        if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("pinned pointer tables: ") + hipGetErrorString(e));
+    }
     if (prev >= 0) (void)hipSetDevice(prev);
     if (rc) {
         std::string keep = mdpe::get_last_error();
@@ -496,6 +716,7 @@ int batch_info(const mdpe_batch *b, mdpe_batch_info *o) {
     o->grid = b->grid;
     o->m1 = b->m1;
     o->m2 = b->m2;
+    o->workspace_bytes = b->ws_bytes;
     return MDPE_OK;
 }
 
@@ -555,30 +776,54 @@ int batch_launch_graph(mdpe_batch *b, void *stream) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     BHIP(hipSetDevice(b->device));
+    int rc = launch_graph_on(b, (hipStream_t)stream);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return rc;
+}
+
+int eval_and_diff_batch(mdpe_batch *b, const double *const *coeff, const double *const *z, double *const *value,
+                        double *const *grad, void *workspace, void *stream) {
+    if (!b || !coeff || !z || !value || !grad || !workspace) return bfail(MDPE_EINVAL, "NULL argument");
+    if (b->device < 0) return bfail(MDPE_EINVAL, "host-only batch");
+    if (((uintptr_t)workspace) % 256) return bfail(MDPE_EINVAL, "workspace must be 256-byte aligned");
+    bool changed = !b->buffers_set;
+    for (int p = 0; p < b->count; ++p) {
+        if (!coeff[p] || !z[p] || !value[p] || !grad[p])
+            return bfail(MDPE_EINVAL, "NULL buffer for instance " + std::to_string(p));
+    }
+    for (int p = 0; p < b->count; ++p) {
+        mdpe::BatchInst &I = b->insts[p];
+        double *A = (double *)((char *)workspace + b->ws_off[p]);
+        changed |= I.A != A || I.coeff != coeff[p] || I.z != z[p] || I.value != value[p] || I.grad != grad[p];
+        I.A = A;
+        I.coeff = coeff[p];
+        I.z = z[p];
+        I.value = value[p];
+        I.grad = grad[p];
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    BHIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
     int rc = MDPE_OK;
-    if (!b->exec) {
-        // capture [reset, persistent kernel] once on a private stream
-        if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-        rc = launch_any(b, b->cap, true);  // attributes and grid, outside the capture
-        if (!rc) {
-            BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-            rc = launch_any(b, b->cap);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(b->cap, &g);
-            if (!rc && e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-            if (!rc) {
-                b->graph = g;
-                e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-                if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-            } else if (g) {
-                (void)hipGraphDestroy(g);
-            }
+    if (changed) {
+        // stream-ordered rebinding: the table goes through a pinned buffer
+        // whose previous copy (kRing rebinds ago) has run by now, unless the
+        // caller is more than kRing rebinds ahead of the device
+        const int r = b->ring_next;
+        b->ring_next = (r + 1) % mdpe_batch::kRing;
+        hipError_t e = b->ring_used[r] ? hipEventSynchronize(b->ring_ev[r]) : hipSuccess;
+        if (e == hipSuccess) {
+            std::memcpy(b->ring[r], b->insts.data(), sizeof(mdpe::BatchInst) * (size_t)b->count);
+            e = hipMemcpyAsync(b->d_insts, b->ring[r], sizeof(mdpe::BatchInst) * (size_t)b->count,
+                               hipMemcpyHostToDevice, st);
         }
+        if (e == hipSuccess) e = hipEventRecord(b->ring_ev[r], st);
+        if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("binding the pointer table: ") + hipGetErrorString(e));
+        b->ring_used[r] = true;
+        b->buffers_set = !rc;
     }
-    if (!rc) {
-        hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
-        if (e != hipSuccess) rc = bfail(MDPE_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-    }
+    if (!rc) rc = launch_graph_on(b, st);
     if (prev >= 0) (void)hipSetDevice(prev);
     return rc;
 }

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
     gather_item(A, value, grad, out_slots[o], o, c, n, d, m);
 }
 
-// planar [m][count][d+1] series src[e] -> slot dst[e], for e < nentries
+// planar [m][count][d+1] series src[e] -> slot dst[e] (skipped when -1), for e < count
 __global__ __launch_bounds__(256) void planar_to_slots_kernel(double *__restrict__ A, const double *__restrict__ src,
                                                               int count, const int *__restrict__ dst, long total,
                                                               int d, int m) {
@@ -114,6 +114,7 @@ __global__ __launch_bounds__(256) void planar_to_slots_kernel(double *__restrict
     const int d1 = d + 1;
     const int e = (int)(idx / d1);
     const int c = (int)(idx - (long)e * d1);
+    if (dst[e] < 0) return;
     double *to = A + (long)dst[e] * d1 * m + (long)c * m;
     for (int l = 0; l < m; ++l) to[l] = src[((long)l * count + e) * d1 + c];
 }
@@ -467,14 +468,14 @@ int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double 
     return MDPE_OK;
 }
 
-int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
-                 void *stream, mdpe_profiler *prof) {
+int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, const double *grad, double *coeff_bar,
+                 double *z_bar, void *stream, mdpe_profiler *prof) {
     if (!pl) return fail(MDPE_EINVAL, "plan is NULL");
     if (pl->device < 0) return fail(MDPE_EINVAL, "host-only plan (device -1) cannot evaluate");
     const mdpe::Plan &P = pl->P;
     if (!(P.flags & mdpe::kKeepMonomialValues))
         return fail(MDPE_EINVAL, "the plan was built without MDPE_KEEP_MONOMIAL_VALUES");
-    if (!ybar || !workspace || !coeff_bar || !z_bar) return fail(MDPE_EINVAL, "NULL buffer");
+    if (!ybar || !workspace || !grad || !coeff_bar || !z_bar) return fail(MDPE_EINVAL, "NULL buffer");
     if (((uintptr_t)workspace) % 256) return fail(MDPE_EINVAL, "workspace must be 256-byte aligned");
     DeviceGuard g(pl->device);
     if (!g.ok) return fail(MDPE_EDEVICE, "cannot select the plan's device");
@@ -486,6 +487,13 @@ int adjoint_impl(const mdpe_plan *pl, const double *ybar, void *workspace, doubl
     hipLaunchKernelGGL(mdpe::planar_to_slots_kernel, dim3((unsigned)((d1 + 255) / 256)), dim3(256), 0, st, A, ybar, 1,
                        pl->d_ybar, (long)d1, P.d, P.m);
     LAUNCH_CHECK("planar_to_slots_kernel");
+    {
+        // the caller's gradient g_i into the slots the correlations read
+        const long tg = (long)P.n * d1;
+        hipLaunchKernelGGL(mdpe::planar_to_slots_kernel, dim3((unsigned)((tg + 255) / 256)), dim3(256), 0, st, A, grad,
+                           P.n, pl->d_out + 1, tg, P.d, P.m);
+        LAUNCH_CHECK("planar_to_slots_kernel");
+    }
     if ((rc = record(prof, 0, st, false))) return rc;
     const int nj = (int)P.corr.size();
     switch (P.m) {
@@ -753,15 +761,15 @@ int md_elementwise(int op, int m, int64_t count, const double *x, const double *
     return MDPE_OK;
 }
 
-int eval_adjoint(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar, double *z_bar,
-                 void *stream) {
-    return adjoint_impl(pl, ybar, workspace, coeff_bar, z_bar, stream, nullptr);
+int eval_adjoint(const mdpe_plan *pl, const double *ybar, void *workspace, const double *grad, double *coeff_bar,
+                 double *z_bar, void *stream) {
+    return adjoint_impl(pl, ybar, workspace, grad, coeff_bar, z_bar, stream, nullptr);
 }
 
-int eval_adjoint_profiled(const mdpe_plan *pl, const double *ybar, void *workspace, double *coeff_bar,
-                          double *z_bar, void *stream, mdpe_profiler *prof) {
+int eval_adjoint_profiled(const mdpe_plan *pl, const double *ybar, void *workspace, const double *grad,
+                          double *coeff_bar, double *z_bar, void *stream, mdpe_profiler *prof) {
     if (!prof) return fail(MDPE_EINVAL, "profiler is NULL");
-    return adjoint_impl(pl, ybar, workspace, coeff_bar, z_bar, stream, prof);
+    return adjoint_impl(pl, ybar, workspace, grad, coeff_bar, z_bar, stream, prof);
 }
 
 int plan_reverse_jobs(const mdpe_plan *pl, int32_t *rows) {

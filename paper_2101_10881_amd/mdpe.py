@@ -73,7 +73,7 @@ class BatchTile(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("n_tasks", ctypes.c_int64), ("n_conv_tasks", ctypes.c_int64),
                 ("n_add_tasks", ctypes.c_int64), ("lds_bytes", ctypes.c_int64), ("grid", ctypes.c_int32),
-                ("m1", ctypes.c_int32), ("m2", ctypes.c_int32)]
+                ("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,13 +109,16 @@ def lib():
     L.profiler_set_classes.argtypes = [_vp, ctypes.c_uint32]
     L.profiler_destroy.restype = None
     L.md_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp]
-    L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
-    L.eval_adjoint_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.eval_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.eval_adjoint_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.plan_reverse_jobs.argtypes = [_vp, _i32p]
     L.check_plan_jobs.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i32p, ctypes.c_int64, _i32p,
                                   ctypes.c_int64, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
-    L.plan_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(BatchTile), ctypes.c_int,
-                             ctypes.POINTER(_vp)]
+    L.plan_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(_vp)]
+    L.plan_batch_tiles.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(BatchTile), ctypes.c_int,
+                                   ctypes.POINTER(_vp)]
+    L.eval_and_diff_batch.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(_vp), _vp, _vp]
     L.batch_info.argtypes = [_vp, ctypes.POINTER(BatchInfo)]
     L.batch_tasks.argtypes = [_vp, _i32p]
     L.batch_set_buffers.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -297,14 +300,15 @@ def eval_and_diff_profiled(plan: Plan, coeff, z, value, grad, workspace, prof: P
                                         _ptr(workspace), _stream(stream), prof._h))
 
 
-def eval_adjoint(plan: Plan, ybar, workspace, coeff_bar, z_bar, stream=None, profiler=None):
-    """Enqueue the reverse pass (plan built with MDPE_KEEP_MONOMIAL_VALUES)."""
+def eval_adjoint(plan: Plan, ybar, workspace, grad, coeff_bar, z_bar, stream=None, profiler=None):
+    """Enqueue the reverse pass (plan built with MDPE_KEEP_MONOMIAL_VALUES):
+    workspace and grad from the preceding eval_and_diff."""
     if profiler is None:
-        _check(lib().eval_adjoint(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(coeff_bar), _ptr(z_bar),
-                                  _stream(stream)))
+        _check(lib().eval_adjoint(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(grad), _ptr(coeff_bar),
+                                  _ptr(z_bar), _stream(stream)))
     else:
-        _check(lib().eval_adjoint_profiled(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(coeff_bar), _ptr(z_bar),
-                                           _stream(stream), profiler._h))
+        _check(lib().eval_adjoint_profiled(plan.handle, _ptr(ybar), _ptr(workspace), _ptr(grad), _ptr(coeff_bar),
+                                           _ptr(z_bar), _stream(stream), profiler._h))
 
 
 def md_elementwise(op, x, y, z, stream=None):
@@ -337,7 +341,7 @@ class Polynomial:
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
-                 stream_operands=None, asap_layers=False, fused_layers=None):
+                 stream_operands=None, asap_layers=False, fused_layers=None, alloc_workspace=True):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
@@ -355,27 +359,33 @@ class Polynomial:
         self.complex = bool(complex)
         self._lead = (2, self.m) if complex else (self.m,)
         nbytes = int(self.plan.info["workspace_bytes"])
-        # 256-byte aligned by the caching allocator
-        self.workspace = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
+        # 256-byte aligned by the caching allocator; alloc_workspace=False
+        # leaves it to the caller (a view of a batch's shared workspace)
+        self.workspace = (torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.device)
+                          if alloc_workspace else None)
 
     @classmethod
     def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False,
-                     fused_layers=None):
+                     fused_layers=None, alloc_workspace=True):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
-                   getattr(w, "exps", None), stream_operands, asap_layers, fused_layers)
+                   getattr(w, "exps", None), stream_operands, asap_layers, fused_layers, alloc_workspace)
 
     def new_workspace(self):
         import torch
         return torch.empty_like(self.workspace)
 
-    def adjoint(self, ybar, workspace=None, stream=None, profiler=None):
-        """Reverse pass after eval_and_diff on `workspace` (default: this object's)."""
+    def adjoint(self, ybar, grad, workspace=None, stream=None, profiler=None):
+        """Reverse pass after eval_and_diff on `workspace` (default: this
+        object's), with the gradient `grad` that call returned."""
         import torch
         if ybar.dtype != torch.float64 or tuple(ybar.shape) != (self.m, self.d + 1) or not ybar.is_contiguous():
             raise ValueError(f"ybar: need a contiguous float64 tensor of shape {(self.m, self.d + 1)}")
+        gshape = (self.m, self.n, self.d + 1)
+        if grad.dtype != torch.float64 or tuple(grad.shape) != gshape or not grad.is_contiguous():
+            raise ValueError(f"grad: need a contiguous float64 tensor of shape {gshape}")
         cbar = torch.empty((self.m, self.N + 1, self.d + 1), dtype=torch.float64, device=self.device)
         zbar = torch.empty((self.m, self.n, self.d + 1), dtype=torch.float64, device=self.device)
-        eval_adjoint(self.plan, ybar, self.workspace if workspace is None else workspace, cbar, zbar, stream,
+        eval_adjoint(self.plan, ybar, self.workspace if workspace is None else workspace, grad, cbar, zbar, stream,
                      profiler)
         return cbar, zbar
 
@@ -405,23 +415,33 @@ class Polynomial:
         return value, grad
 
 
+TUNE_CACHE = os.path.join(_HERE, "tune_cache.json")
+
+
 class Batch:
     """plan_batch over Plan objects (kept alive by the batch).
 
+    tune_cache: path of the autotuner's cache (plan_batch reads it); else
     tiles: optional list of dicts {m, d, jobs_per_group, groups_per_task,
-    add_items_per_task} (zero / missing fields take the defaults).
+    add_items_per_task} (zero / missing fields take the defaults),
+    passed to plan_batch_tiles.
     """
 
-    def __init__(self, plans, tiles=None):
+    def __init__(self, plans, tiles=None, tune_cache=None):
         self.plans = list(plans)
         arr = (_vp * len(self.plans))(*[p.handle.value for p in self.plans])
-        tl = list(tiles or [])
-        tarr = (BatchTile * max(len(tl), 1))()
-        for q, t in enumerate(tl):
-            tarr[q] = BatchTile(int(t["m"]), int(t["d"]), int(t.get("jobs_per_group", 0)),
-                                int(t.get("groups_per_task", 0)), int(t.get("add_items_per_task", 0)))
         h = _vp()
-        _check(lib().plan_batch(arr, len(self.plans), tarr, len(tl), ctypes.byref(h)))
+        if tune_cache is not None:
+            if tiles is not None:
+                raise ValueError("give tiles or tune_cache, not both")
+            _check(lib().plan_batch(arr, len(self.plans), os.fsencode(tune_cache), ctypes.byref(h)))
+        else:
+            tl = list(tiles or [])
+            tarr = (BatchTile * max(len(tl), 1))()
+            for q, t in enumerate(tl):
+                tarr[q] = BatchTile(int(t["m"]), int(t["d"]), int(t.get("jobs_per_group", 0)),
+                                    int(t.get("groups_per_task", 0)), int(t.get("add_items_per_task", 0)))
+            _check(lib().plan_batch_tiles(arr, len(self.plans), tarr, len(tl), ctypes.byref(h)))
         self._h = h
 
     def __del__(self):
@@ -447,6 +467,15 @@ class Batch:
         self._keep = (coeffs, zs, values, grads, workspaces)
         _check(lib().batch_set_buffers(self._h, arr(coeffs), arr(zs), arr(values), arr(grads), arr(workspaces)))
 
+    def eval_and_diff(self, coeffs, zs, values, grads, workspace, stream=None):
+        """eval_and_diff_batch: one graph replay on `stream`, rebinding the
+        pointer table on the stream when a buffer changed."""
+        def arr(ts):
+            return (_vp * len(ts))(*[t.data_ptr() for t in ts])
+        self._keep_eval = (coeffs, zs, values, grads, workspace)
+        _check(lib().eval_and_diff_batch(self._h, arr(coeffs), arr(zs), arr(values), arr(grads), _ptr(workspace),
+                                         _stream(stream)))
+
     def launch(self, stream=None):
         _check(lib().batch_launch(self._h, _stream(stream)))
 
@@ -461,15 +490,31 @@ class Batch:
 
 
 class BatchedPolynomials:
-    """Polynomials (one Polynomial each, with its plan and workspace) run as one batch."""
+    """Polynomials (one Polynomial each, with its plan) run as one batch.
 
-    def __init__(self, workloads, device=None, tiles=None):
+    The instances share one workspace of batch_info().workspace_bytes; each
+    Polynomial's workspace is its part of it, so the instances can also be
+    evaluated one by one (Polynomial.eval_and_diff) on the same memory.
+    tune_cache: the autotuner's cache, read by plan_batch; else tiles (a list
+    of tile dicts, plan_batch_tiles)."""
+
+    def __init__(self, workloads, device=None, tiles=None, tune_cache=None):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
-        self.polys = [Polynomial.for_workload(w, self.device) for w in workloads]
-        self.batch = Batch([P.plan for P in self.polys], tiles)
+        self.polys = [Polynomial.for_workload(w, self.device, alloc_workspace=False) for w in workloads]
+        self._tiles, self._tune_cache = tiles, tune_cache
+        self.batch = Batch([P.plan for P in self.polys], tiles, tune_cache)
+        total = int(self.batch.info()["workspace_bytes"])
+        self.workspace = torch.empty(max(total // 8, 1), dtype=torch.float64, device=self.device)
+        off = 0
+        for P in self.polys:
+            nb = int(P.plan.info["workspace_bytes"])
+            P.workspace = self.workspace[off // 8: off // 8 + max(nb // 8, 1)]
+            off += (nb + 255) // 256 * 256
+        if off != total:
+            raise RuntimeError(f"batch workspace layout: {off} bytes against {total}")
         self.values = [torch.empty((P.m, P.d + 1), dtype=torch.float64, device=self.device) for P in self.polys]
         self.grads = [torch.empty((P.m, P.n, P.d + 1), dtype=torch.float64, device=self.device) for P in self.polys]
 
@@ -478,6 +523,14 @@ class BatchedPolynomials:
             P._check_inputs(c, z)
         self._inputs = (coeffs, zs)
         self.batch.set_buffers(coeffs, zs, self.values, self.grads, [P.workspace for P in self.polys])
+
+    def eval_and_diff(self, coeffs, zs, stream=None):
+        """All instances in one graph replay (eval_and_diff_batch); returns the
+        per-instance value and gradient tensors."""
+        for P, c, z in zip(self.polys, coeffs, zs):
+            P._check_inputs(c, z)
+        self.batch.eval_and_diff(coeffs, zs, self.values, self.grads, self.workspace, stream)
+        return self.values, self.grads
 
     def set_tiles(self, tiles):
         """Rebuild the task queue with other tiles (plans and buffers are kept)."""

@@ -7,12 +7,26 @@ import pytest
 from paper_2101_10881_amd import mdpe
 
 
+# the boundary's calls: plan once, evaluate per call (Section 5), batched,
+# reverse pass, release, error strings
+BOUNDARY = {"plan_polynomial", "plan_info", "eval_and_diff", "plan_batch", "eval_and_diff_batch", "eval_adjoint",
+            "plan_destroy", "batch_destroy", "last_error_string"}
+
+
 def test_header_symbols_exported():
     L = mdpe.lib()
     syms = mdpe.header_symbols()
-    assert {"plan_polynomial", "eval_and_diff", "plan_destroy", "last_error_string"} <= set(syms)
+    assert BOUNDARY <= set(syms), BOUNDARY - set(syms)
     for s in syms:
         assert hasattr(L, s), s
+
+
+def test_boundary_calls_reject_null_arguments():
+    L = mdpe.lib()
+    assert L.eval_and_diff_batch(None, None, None, None, None, None, None) == mdpe.MDPE_EINVAL
+    assert L.eval_adjoint(None, None, None, None, None, None, None) == mdpe.MDPE_EINVAL
+    assert L.plan_batch(None, 0, None, None) == mdpe.MDPE_EINVAL
+    L.batch_destroy(None)
 
 
 def test_host_only_plan_cannot_evaluate():

@@ -105,3 +105,67 @@ def test_equal_instances_keep_one_queue_each():
     for p in range(16):
         assert len(np.unique(rows[rows[:, 0] == p, 5])) == 1
     assert np.all(np.bincount(rows[:, 5], minlength=8) > 0)
+
+
+# ------------------------------------------------------- the tune cache --
+# plan_batch reads the autotuner's JSON cache itself, so a C caller gets the
+# tuned tiles; the tiles it finds must give the same task table as passing
+# them directly (plan_batch_tiles).
+
+def _mixed(count=24, seed=9):
+    rng = np.random.default_rng(seed)
+    ws = []
+    for q in range(count):
+        m = int(rng.choice([2, 4]))
+        d = int(rng.choice([8, 16, 64, 128]))
+        n = int(rng.integers(4, 12))
+        N = int(rng.integers(4, 40))
+        ws.append(W.random_poly(f"t{q}", m, d, n, N, rng.integers(2, min(n, 6) + 1, size=N), q))
+    return ws
+
+
+def test_plan_batch_reads_the_committed_tune_cache():
+    import json
+    ws = _mixed()
+    plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
+    tiles = json.load(open(mdpe.TUNE_CACHE))["gfx950"]["tiles"]
+    a = mdpe.Batch(plans, tune_cache=mdpe.TUNE_CACHE)
+    b = mdpe.Batch(plans, tiles=tiles)
+    c = mdpe.Batch(plans)
+    assert np.array_equal(a.tasks(), b.tasks())
+    assert not np.array_equal(a.tasks(), c.tasks())     # the cache changes the tiles of its buckets
+
+
+def test_tune_cache_without_this_architecture_gives_the_defaults(tmp_path):
+    ws = _mixed(8)
+    plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
+    f = tmp_path / "cache.json"
+    f.write_text('{"gfx942": {"tiles": [{"m": 2, "d": 8, "jobs_per_group": 3}]}, "note": [1, 2.5, true, null]}')
+    assert np.array_equal(mdpe.Batch(plans, tune_cache=str(f)).tasks(), mdpe.Batch(plans).tasks())
+
+
+@pytest.mark.parametrize("text,words", [
+    (None, "cannot read"),
+    ("{not json", "not a JSON object"),
+    ('[1, 2]', "not a JSON object"),
+    ('{"gfx950": {"tiles": 3}}', "no tile list"),
+    ('{"gfx950": {"tiles": [{"d": 8, "jobs_per_group": 2}]}}', "integer m, d"),
+    ('{"gfx950": {"tiles": [{"m": 2, "d": 8, "jobs_per_group": 2.5}]}}', "integer m, d"),
+])
+def test_bad_tune_caches_are_rejected(tmp_path, text, words):
+    ws = _mixed(4)
+    plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
+    f = tmp_path / "cache.json"
+    if text is not None:
+        f.write_text(text)
+    with pytest.raises(mdpe.MdpeError) as e:
+        mdpe.Batch(plans, tune_cache=str(f))
+    assert e.value.code == mdpe.MDPE_EINVAL and words in str(e.value)
+
+
+def test_batch_workspace_is_the_instances_parts():
+    ws = _mixed(10)
+    plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
+    B = mdpe.Batch(plans)
+    want = sum((p.info["workspace_bytes"] + 255) // 256 * 256 for p in plans)
+    assert B.info()["workspace_bytes"] == want

@@ -179,3 +179,39 @@ def test_batch_of_one_dealt_over_every_xcd(name, build, grid):
     assert len(np.unique(B.batch.tasks()[:, 5])) == 8
     _check(got[0], want, name)
     _check(got[1], want, name + " replay")
+
+
+def test_eval_and_diff_batch_rebinds_on_the_stream(oracle_lib):
+    """eval_and_diff_batch through the C ABI, with the tiles plan_batch reads
+    from the tune cache: three calls without a host synchronisation between
+    them -- new input buffers on the second (the pointer table is rebound on
+    the stream), the first buffers again on the third -- each bit for bit equal
+    to eval_and_diff of every instance."""
+    import torch
+    from paper_2101_10881_amd import mdpe
+    dev = torch.device("cuda", 0)
+    ws = _instances(20, 11, ds=(0, 8, 16, 33, 64, 128))
+    B = mdpe.BatchedPolynomials(ws, dev, tune_cache=mdpe.TUNE_CACHE)
+    c1 = [torch.from_numpy(w.coeff).to(dev) for w in ws]
+    z1 = [torch.from_numpy(w.z).to(dev) for w in ws]
+    c2 = [-c for c in c1]                     # exact: every limb negated
+    z2 = [z.clone() for z in z1]
+    print(f"eval_and_diff_batch: {len(ws)} instances, workspace {B.batch.info()['workspace_bytes']} bytes", flush=True)
+    outs = []
+    for cs, zs in ((c1, z1), (c2, z2), (c1, z1)):
+        vals, grads = B.eval_and_diff(cs, zs)
+        outs.append(([v.clone() for v in vals], [g.clone() for g in grads]))   # stream-ordered copies
+    torch.cuda.synchronize()
+    B.batch.status()
+    want1 = _plain(ws)
+    for w in ws:
+        w.coeff = -w.coeff
+    want2 = _plain(ws)
+    for w in ws:
+        w.coeff = -w.coeff
+    for r, want in ((0, want1), (1, want2), (2, want1)):
+        got = [(v.cpu().numpy(), g.cpu().numpy()) for v, g in zip(*outs[r])]
+        _check(got, want, f"eval_and_diff_batch call {r}")
+    v, g = oracle_lib.eval_workload(ws[3])
+    assert_bitexact(outs[0][0][3].cpu().numpy(), v, "oracle value 3")
+    assert_bitexact(outs[0][1][3].cpu().numpy(), g, "oracle grad 3")

@@ -73,7 +73,7 @@ def test_fused_layers_keep_monomials_for_the_adjoint():
         P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True, fused_layers=fused)
         assert (P.plan.info["fused_components"] > 0) == fused
         v, g = P.eval_and_diff(torch.from_numpy(w.coeff).to(dev), torch.from_numpy(w.z).to(dev))
-        cb, zb = P.adjoint(ybar)
+        cb, zb = P.adjoint(ybar, g)
         torch.cuda.synchronize()
         out.append([t.cpu().numpy() for t in (v, g, cb, zb)])
     for a, b, what in zip(out[0], out[1], ("value", "grad", "coeff_bar", "z_bar")):
@@ -82,6 +82,7 @@ def test_fused_layers_keep_monomials_for_the_adjoint():
 
 @pytest.mark.parametrize("m,d,poly,expect", [(4, 127, "p2", True), (4, 128, "p2", False), (5, 31, "p2", True),
                                              (5, 32, "p2", False), (8, 8, "p2", True), (8, 9, "p2", False),
+                                             (10, 31, "p2", True), (10, 32, "p2", False),
                                              (2, 63, "p1", True), (2, 64, "p1", False)])
 def test_default_choice_at_its_limits(oracle_lib, m, d, poly, expect):
     # either side of the automatic rule's degree limits, bitwise against the oracle

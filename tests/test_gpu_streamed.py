@@ -26,7 +26,7 @@ def _run(w, stream, keep=False, ybar=None):
     val, grad = P.eval_and_diff(coeff, z)
     out = [val, grad]
     if ybar is not None:
-        out += list(P.adjoint(torch.from_numpy(np.ascontiguousarray(ybar)).to(dev)))
+        out += list(P.adjoint(torch.from_numpy(np.ascontiguousarray(ybar)).to(dev), grad))
     torch.cuda.synchronize()
     return P.plan.info, [t.cpu().numpy() for t in out]
 
