@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one torch copy of this size before timing (for HBM counter calibration)")
-    ap.add_argument("--check", action="store_true", help="compare the output digest with the oracle's")
+    ap.add_argument("--no-check", dest="check", action="store_false",
+                    help="skip comparing the output digest with the oracle's (compared by default)")
     ap.add_argument("--workload", default="p1", choices=["p1", "batch", "sweep"],
                     help="p1: deca double d=152 (the headline); batch: 512 mixed instances vs separate launches; "
                          "sweep: the paper's precision x degree tables for p1, p2, p3")
@@ -51,8 +52,15 @@ def parse():
                     help="sweep: raise half of the variable occurrences to exponents 2..emax")
     ap.add_argument("--instances", type=int, default=512, help="batch: number of instances")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the side measurements (batched vs plain, autograd, complex, streamed, layering, seeds)")
+                    help="skip the other workloads and side measurements (double double d=8, quad double p2, "
+                         "the batch, the autograd pass, complex, streamed, layering, seeds)")
+    ap.add_argument("--workload-steps", type=int, default=20, help="timed steps of each of the other workloads")
     return ap.parse_args()
+
+
+def progress(msg):
+    """A progress line on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_digest():
@@ -117,6 +125,142 @@ def cpu_baseline(target_s):
                               "sample": f"first {K1} monomials, 1 thread ({dt1:.1f} s wall)"}}
 
 
+def _cpu_info():
+    cores = len(os.sched_getaffinity(0))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return cores, model
+
+
+def _step_times(fn, steps, warmup):
+    """Per-step milliseconds of fn() from HIP events between consecutive steps
+    on the current stream (inputs resident, no host synchronisation inside)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    marks[0].record(stream)
+    for k in range(steps):
+        fn()
+        marks[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    return {"median": round(statistics.median(per), 4), "min": round(per[0], 4), "max": round(per[-1], 4),
+            "mean": round(marks[0].elapsed_time(marks[-1]) / steps, 4), "steps": steps}
+
+
+def _rate(flop, ms):
+    return {"GFLOPs": round(flop / (ms * 1e-3) / 1e9, 2), "frac_fp64_peak": round(flop / (ms * 1e-3) / 1e12 /
+                                                                                    FP64_PEAK_TFLOPS, 5)}
+
+
+def _oracle_timed(fn, reps=3):
+    """Median wall seconds of fn() over reps runs (the CPU oracle, all host cores)."""
+    times, out = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        times.append(time.perf_counter() - t0)
+    return statistics.median(times), out
+
+
+def _bits_equal(gpu, want):
+    import numpy as np
+    g = np.ascontiguousarray(gpu.detach().cpu().numpy(), dtype=np.float64).view(np.uint64)
+    return bool(np.array_equal(g, np.ascontiguousarray(want, dtype=np.float64).view(np.uint64)))
+
+
+def measure_plain_workload(w, steps, warmup):
+    """One plain workload: eval_and_diff per step, event-timed, beside the
+    oracle on all host cores for the same inputs; outputs compared bitwise."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2101_10881_amd import flops, mdpe
+
+    dev = torch.device("cuda", 0)
+    P = mdpe.Polynomial.for_workload(w, dev)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    value, grad = P.eval_and_diff(coeff, z)
+    ms = _step_times(lambda: P.eval_and_diff(coeff, z, value, grad), steps, warmup)
+    info = P.plan.info
+    work = info["n_conv"] * flops.conv_flops(w.m, w.d) + info["n_add"] * flops.add_flops(w.m, w.d)
+    cores, model = _cpu_info()
+    sec, (ov, og) = _oracle_timed(lambda: O.eval_workload(w, nthreads=cores))
+    out = {"workload": w.name, "m": w.m, "d": w.d, "n": w.n, "N": w.N, "n_conv": info["n_conv"],
+           "n_add": info["n_add"], "conv_launches": info["n_layers"] if not info["fused_components"] else 1,
+           "fused_layers": bool(info["fused_components"]), "ms_per_step": ms, "flop_per_step": work,
+           **_rate(work, ms["median"]),
+           "bitexact_vs_oracle": _bits_equal(value, ov) and _bits_equal(grad, og),
+           "cpu_oracle": {"seconds": round(sec, 5), **_rate(work, sec * 1e3), "cores": cores, "cpu_model": model,
+                          "sample": "the whole workload, median of 3 runs"}}
+    out["gpu_vs_cpu"] = round(sec * 1e3 / ms["median"], 1)
+    return out
+
+
+def measure_autograd_workload(steps, warmup):
+    """The differentiation workload: octo-double p1 at d = 32 through
+    torch.autograd.Function (forward keeping the monomial products, backward
+    the adjoint kernel), beside the oracle's value, gradient and adjoints."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2101_10881_amd import flops, mdpe
+    from paper_2101_10881_amd import workloads as W
+    from paper_2101_10881_amd.autograd import poly_eval
+
+    dev = torch.device("cuda", 0)
+    w = W.p1(m=8, d=32)
+    P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    ybar_np = W.upstream_adjoint(w.m, w.d, seed=1)
+    ybar = torch.from_numpy(ybar_np).to(dev)
+    value, grad = P.eval_and_diff(coeff, z)
+    fwd = _step_times(lambda: P.eval_and_diff(coeff, z, value, grad), steps, warmup)
+    rev = _step_times(lambda: P.adjoint(ybar, grad), steps, warmup)
+    cr = coeff.clone().requires_grad_(True)
+    zr = z.clone().requires_grad_(True)
+
+    def step():
+        cr.grad = None
+        zr.grad = None
+        v, _ = poly_eval(cr, zr, P)
+        v.backward(ybar)
+
+    ag = _step_times(step, steps, warmup)
+    info = P.plan.info
+    fwd_work = info["n_conv"] * flops.conv_flops(w.m, w.d) + info["n_add"] * flops.add_flops(w.m, w.d)
+    rev_work = info["n_reverse"] * flops.conv_flops(w.m, w.d)
+    cores, model = _cpu_info()
+
+    def oracle():
+        ov, og = O.eval_workload(w, nthreads=cores)
+        oc, oz = O.eval_adjoint(w.m, w.d, w.n, w.nvars, w.vars, w.z, og, ybar_np, nthreads=cores)
+        return ov, og, oc, oz
+
+    sec, (ov, og, oc, oz) = _oracle_timed(oracle)
+    exact = (_bits_equal(value, ov) and _bits_equal(grad, og) and _bits_equal(cr.grad, oc) and
+             _bits_equal(zr.grad, oz))
+    work = fwd_work + rev_work
+    return {"workload": w.name + "_autograd", "m": w.m, "d": w.d, "n": w.n, "N": w.N,
+            "forward_conv_jobs": info["n_conv"], "reverse_jobs": info["n_reverse"],
+            "forward_ms": fwd, **{"forward_" + k: v for k, v in _rate(fwd_work, fwd["median"]).items()},
+            "reverse_ms": rev, **{"reverse_" + k: v for k, v in _rate(rev_work, rev["median"]).items()},
+            "autograd_step_ms": ag, **_rate(work, ag["median"]), "flop_per_step": work,
+            "bitexact_vs_oracle": exact,
+            "cpu_oracle": {"seconds": round(sec, 5), **_rate(work, sec * 1e3), "cores": cores, "cpu_model": model,
+                           "sample": "value, gradient and adjoints of the whole workload, median of 3 runs"},
+            "gpu_vs_cpu": round(sec * 1e3 / ag["median"], 1)}
+
+
 def measure_batch(instances, steps, warmup):
     """The batched workload: `instances` polynomials (n 8..64, N 16..1024,
     2..8 variables per monomial, d in {8,16,32,64,128}, m in {2,4}) in one
@@ -130,7 +274,7 @@ def measure_batch(instances, steps, warmup):
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
     ws = W.mixed_batch(instances, seed=1)
-    B = mdpe.BatchedPolynomials(ws, dev, tiles=load_tiles())
+    B = mdpe.BatchedPolynomials(ws, dev, tune_cache=mdpe.TUNE_CACHE)
     coeffs = [torch.from_numpy(w.coeff).to(dev) for w in ws]
     zs = [torch.from_numpy(w.z).to(dev) for w in ws]
     B.bind(coeffs, zs)
@@ -164,23 +308,67 @@ def measure_batch(instances, steps, warmup):
     B.batch.status()
     same = all(torch.equal(x.view(torch.int64), y.view(torch.int64))
                for x, y in zip(B.values + B.grads, pv + pg))
+    # the boundary's batched call: one graph replay per step over one workspace
+    ms_call = _step_times(lambda: B.eval_and_diff(coeffs, zs), steps, warmup)
+    same_call = all(torch.equal(x.view(torch.int64), y.view(torch.int64))
+                    for x, y in zip(B.values + B.grads, pv + pg))
     info = B.batch.info()
+    # the default tiles on the same kernel, for the tuner's gain
+    D = mdpe.BatchedPolynomials(ws, dev)
+    D.bind(coeffs, zs)
+    ms_default = timed(lambda: D.run(graph=True), steps)
+    D.batch.status()
+    same_default = all(torch.equal(x.view(torch.int64), y.view(torch.int64))
+                       for x, y in zip(D.values + D.grads, pv + pg))
+    del D
     return {
         "workload": f"mixed_batch_{instances}", "instances": instances, "seed": 1,
         "GFLOPs": round(work / (ms_graph * 1e-3) / 1e9, 1),
+        "frac_fp64_peak": round(work / (ms_graph * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 5),
+        "flop_per_step": work,
         "batched_ms": {"graph": round(ms_graph, 4), "launch": round(ms_batch, 4)},
+        "eval_and_diff_batch_ms": ms_call,
         "plain_ms": round(ms_plain, 4),
         "speedup_vs_plain": round(ms_plain / ms_graph, 3),
-        "bitexact_vs_plain": bool(same),
+        "bitexact_vs_plain": bool(same and same_call and same_default),
+        "tiles": {"tuned_ms": round(ms_graph, 4), "default_ms": round(ms_default, 4),
+                  "tuned_speedup": round(ms_default / ms_graph, 3), "cache": os.path.relpath(mdpe.TUNE_CACHE, ROOT)},
         "precisions": sorted({P.m for P in B.polys}), "degrees": sorted({P.d for P in B.polys}),
         "n_conv": sum(P.plan.info["n_conv"] for P in B.polys), "n_add": sum(P.plan.info["n_add"] for P in B.polys),
-        "tasks": info["n_tasks"], "persistent_workgroups": info["grid"], "tiles": "autotuned" if load_tiles() else "default",
+        "tasks": info["n_tasks"], "persistent_workgroups": info["grid"],
         "setup_s": round(setup_s, 1),
+        "_outputs": (ws, B),
     }
+
+
+def batch_cpu_baseline(r, every=8):
+    """The oracle on every `every`-th instance of the batch (a bounded
+    sample), all host cores; sampled outputs compared bitwise with the batch's."""
+    from oracle import oracle as O
+    from paper_2101_10881_amd import flops
+
+    ws, B = r.pop("_outputs")
+    cores, model = _cpu_info()
+    idx = list(range(0, len(ws), every))
+    work, exact = 0, True
+    t0 = time.perf_counter()
+    outs = [O.eval_workload(ws[q], nthreads=cores) for q in idx]
+    sec = time.perf_counter() - t0
+    for q, (ov, og) in zip(idx, outs):
+        P = B.polys[q]
+        work += P.plan.info["n_conv"] * flops.conv_flops(P.m, P.d) + P.plan.info["n_add"] * flops.add_flops(P.m, P.d)
+        exact &= _bits_equal(B.values[q], ov) and _bits_equal(B.grads[q], og)
+    r["bitexact_vs_oracle_sample"] = bool(exact)
+    r["cpu_oracle"] = {"seconds": round(sec, 3), **_rate(work, sec * 1e3), "cores": cores, "cpu_model": model,
+                       "sample": f"{len(idx)} of the {len(ws)} instances (every {every}th), one run"}
+    gpu_rate = r["flop_per_step"] / (r["batched_ms"]["graph"] * 1e-3)
+    r["gpu_vs_cpu"] = round(gpu_rate / (work / sec), 1)
+    return r
 
 
 def run_batch(a):
     r = measure_batch(a.instances, a.steps, a.warmup)
+    r.pop("_outputs")
     out = {
         "metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
         "value": r["GFLOPs"], "unit": "GFLOP/s",
@@ -192,43 +380,6 @@ def run_batch(a):
         "batched": r,
     }
     print(json.dumps(out), flush=True)
-
-
-def measure_autograd(steps, warmup):
-    """The differentiation workload: octo-double p1 at d = 32; forward
-    (eval_and_diff keeping the monomial products) and the reverse pass."""
-    import torch
-
-    from paper_2101_10881_amd import mdpe
-    from paper_2101_10881_amd import workloads as W
-
-    dev = torch.device("cuda", 0)
-    w = W.p1(m=8, d=32)
-    P = mdpe.Polynomial.for_workload(w, dev, keep_monomials=True)
-    coeff = torch.from_numpy(w.coeff).to(dev)
-    z = torch.from_numpy(w.z).to(dev)
-    ybar = torch.from_numpy(W.upstream_adjoint(w.m, w.d, seed=1)).to(dev)
-    value, grad = P.eval_and_diff(coeff, z)
-    for _ in range(warmup):
-        P.eval_and_diff(coeff, z, value, grad)
-        P.adjoint(ybar, grad)
-    torch.cuda.synchronize()
-    prof = mdpe.Profiler()
-    stream = torch.cuda.current_stream()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    e[0].record(stream)
-    for _ in range(steps):
-        P.eval_and_diff(coeff, z, value, grad)
-    e[1].record(stream)
-    for _ in range(steps):
-        P.adjoint(ybar, grad, profiler=prof)
-    e[2].record(stream)
-    torch.cuda.synchronize()
-    t = prof.read()
-    return {"workload": w.name, "forward_ms": round(e[0].elapsed_time(e[1]) / steps, 4),
-            "reverse_ms": round(e[1].elapsed_time(e[2]) / steps, 4),
-            "reverse_correlation_ms": round(t["cnv_ms"] / steps, 4),
-            "reverse_jobs": P.plan.info["n_reverse"], "forward_conv_jobs": P.plan.info["n_conv"]}
 
 
 def measure_complex(steps, warmup, m=10, d=152):
@@ -536,18 +687,33 @@ def main():
         "kernel_source_sha256": digest[:16],
     }
     if a.check:
+        # the digests of the oracle's output for this workload, written by
+        # tests/golden/make_digests.py
         g = json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json")))["workloads"]["p1_10d_d152"]
         h = lambda t: hashlib.sha256(t.cpu().numpy().astype("<f8").tobytes()).hexdigest()
         out["check"] = {"value_matches_oracle_digest": h(value) == g["value_sha256"],
                         "grad_matches_oracle_digest": h(grad) == g["grad_sha256"]}
     if not a.no_extras:
-        out["batched_vs_plain"] = measure_batch(a.instances, 3, 1)
-        out["autograd_p1_8d_d32"] = measure_autograd(10, 2)
+        # the other workloads, each beside the oracle on the host cores
+        ks = max(10, a.workload_steps)
+        wl = {}
+        for wk in (W.rand3(), W.p2()):
+            progress(f"workload {wk.name}")
+            wl[wk.name] = measure_plain_workload(wk, ks, 3)
+        progress(f"workload mixed_batch_{a.instances}")
+        r = measure_batch(a.instances, ks, 2)
+        wl[r["workload"]] = batch_cpu_baseline(r)
+        progress("workload p1_8d_d32 autograd")
+        r = measure_autograd_workload(ks, 3)
+        wl[r["workload"]] = r
+        out["workloads"] = wl
+        progress("side measurements")
         out["complex_p1"] = measure_complex(5, 1)
         out["streamed_operands"] = measure_streamed(3, 1)
         out["layer_balancing"] = measure_layering(5, 1)
         out["seed_spread"] = measure_seeds(P, 3)
     if not a.no_cpu_baseline:
+        progress("CPU baseline")
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

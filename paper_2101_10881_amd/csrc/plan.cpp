@@ -242,14 +242,64 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
 // vs 12.9 ms at equal steps).
 constexpr long kSimds = 1024;  // MI355X: 256 CUs x 4 SIMDs
 
-static double layer_cost(const Plan &P, int waves_per_job, int jobs_per_group, int steps, double step_cost) {
+static double layer_cost(const Plan &P, int waves_per_job, int jobs_per_group, int steps, double step_cost,
+                         int from_layer = 1) {
     double c = 0;
-    for (int L = 1; L <= P.n_layers(); ++L) {
+    for (int L = from_layer; L <= P.n_layers(); ++L) {
         const long jobs = P.conv_off[L] - P.conv_off[L - 1];
         const long waves = (jobs + jobs_per_group - 1) / jobs_per_group * waves_per_job;
         c += std::ceil(waves / (double)kSimds) * steps * step_cost;
     }
     return c;
+}
+
+// Staged operands: jobs per wavefront J and wavefronts per job Q for the
+// layers from_layer.. (the others are launched otherwise).
+static void choose_staged_lanes(Plan &P, int from_layer) {
+    const int d = P.d, w = P.w;
+    // Candidates, by the layer cost model: J jobs per wavefront by the lane
+    // schedule (J0 halved down to 1), one job over Q = 2..4 wavefronts,
+    // and for coefficients of at most two doubles the same J dealt to the
+    // lanes in turn (steps weighted by their lower cost).  Fewer jobs per
+    // wavefront or several wavefronts per job pay when layers have fewer
+    // wavefronts than the chip has SIMDs (deep chains such as p2).
+    // (A candidate replaces the default only when estimated 10% faster: the
+    // model ignores staging and per-wavefront costs, e.g. p2 4d d = 64's two jobs
+    // per wavefront measure 4% faster than one although it predicts the
+    // opposite.)  Dealt steps weigh 0.15 (m = 1) or 0.4 (m = 2): measured
+    // on p2 at d = 152.
+    const int J0 = choose_jobs_per_group(d, w);
+    double best = -1;
+    auto consider = [&](LaneSchedule &&ls, bool simple, double c) {
+        if (best < 0 || c < 0.9 * best) {
+            best = c;
+            P.lanes = std::move(ls);
+            P.simple = simple;
+        }
+    };
+    for (int J = J0;; J /= 2) {
+        LaneSchedule ls = make_lane_schedule(d, J);
+        const double c = layer_cost(P, 1, J, ls.steps, 1.0, from_layer);
+        if (w <= 2) {
+            const double sc = layer_cost(P, 1, J, dealt_steps(d, J), w == 1 ? 0.15 : 0.4, from_layer);
+            if (sc < c) {
+                consider(std::move(ls), true, sc);
+                if (J == 1) break;
+                continue;
+            }
+        }
+        consider(std::move(ls), false, c);
+        if (J == 1) break;
+    }
+    for (int Q = 2; Q <= 4 && d + 1 >= kLanes; ++Q) {
+        LaneSchedule ls = make_lane_schedule(d, 1, Q);
+        const double c = layer_cost(P, Q, 1, ls.steps, 1.0, from_layer);
+        consider(std::move(ls), false, c);
+    }
+    // one job's coefficients dealt over Q wavefronts (deep chains of small
+    // layers, such as p2, at one or two doubles per coefficient)
+    for (int Q = 2; Q <= 4 && w <= 2 && d + 1 > (Q - 1) * kLanes; ++Q)
+        consider(make_lane_schedule(d, 1, Q), true, layer_cost(P, Q, 1, dealt_steps(d, 1, Q), w == 1 ? 0.15 : 0.4, from_layer));
 }
 
 // Layer balancing.  The layering above puts every convolution at its
@@ -749,53 +799,7 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
         else
             P.lanes = make_lane_schedule(d, Q > 1 ? 1 : std::max(1, std::min(kLanes, (2 * kLanes + d + 1) / (d + 2))), Q);
     } else {
-        // jobs per wavefront J and wavefronts per job Q by the layer cost model:
-        // fewer jobs per wavefront, or several wavefronts per job, when layers
-        // have fewer wavefronts than the chip has SIMDs (deep chains such as
-        // p2), down to the longest coefficient's d+1 steps
-        // Candidates, by the layer cost model: J jobs per wavefront by the lane
-        // schedule (J0 halved down to 1), one job over Q = 2..4 wavefronts,
-        // and for coefficients of at most two doubles the same J dealt to the
-        // lanes in turn (steps weighted by their lower cost).  Fewer jobs per
-        // wavefront or several wavefronts per job pay when layers have fewer
-        // wavefronts than the chip has SIMDs (deep chains such as p2).
-        // (A candidate replaces the default only when estimated 10% faster: the
-        // model ignores staging and per-wavefront costs, e.g. p2 4d d = 64's two jobs
-        // per wavefront measure 4% faster than one although it predicts the
-        // opposite.)  Dealt steps weigh 0.15 (m = 1) or 0.4 (m = 2): measured
-        // on p2 at d = 152.
-        const int J0 = choose_jobs_per_group(d, w);
-        double best = -1;
-        auto consider = [&](LaneSchedule &&ls, bool simple, double c) {
-            if (best < 0 || c < 0.9 * best) {
-                best = c;
-                P.lanes = std::move(ls);
-                P.simple = simple;
-            }
-        };
-        for (int J = J0;; J /= 2) {
-            LaneSchedule ls = make_lane_schedule(d, J);
-            const double c = layer_cost(P, 1, J, ls.steps, 1.0);
-            if (w <= 2) {
-                const double sc = layer_cost(P, 1, J, dealt_steps(d, J), w == 1 ? 0.15 : 0.4);
-                if (sc < c) {
-                    consider(std::move(ls), true, sc);
-                    if (J == 1) break;
-                    continue;
-                }
-            }
-            consider(std::move(ls), false, c);
-            if (J == 1) break;
-        }
-        for (int Q = 2; Q <= 4 && d + 1 >= kLanes; ++Q) {
-            LaneSchedule ls = make_lane_schedule(d, 1, Q);
-            const double c = layer_cost(P, Q, 1, ls.steps, 1.0);
-            consider(std::move(ls), false, c);
-        }
-        // one job's coefficients dealt over Q wavefronts (deep chains of small
-        // layers, such as p2, at one or two doubles per coefficient)
-        for (int Q = 2; Q <= 4 && w <= 2 && d + 1 > (Q - 1) * kLanes; ++Q)
-            consider(make_lane_schedule(d, 1, Q), true, layer_cost(P, Q, 1, dealt_steps(d, 1, Q), w == 1 ? 0.15 : 0.4));
+        choose_staged_lanes(P, 1);
         // A job over several wavefronts may not write its own first operand
         // (see no_inplace above): rebuild with fresh output slots for the
         // in-place jobs.  The jobs and layers are the same, so is the choice.

@@ -42,6 +42,11 @@ constexpr uint32_t kStageOperands = 8u;    // stage them in LDS (no automatic st
 constexpr uint32_t kAsapLayers = 16u;      // every convolution at its earliest layer (no balancing)
 constexpr uint32_t kFusedLayers = 32u;     // all convolution layers in one launch, per independent component
 constexpr uint32_t kLayerLaunches = 64u;   // one launch per convolution layer (no automatic fusing)
+constexpr uint32_t kChainLaunch = 128u;    // first-operand chains in one pipelined launch (see Plan::pipe_*)
+
+// Chain launch: the code of an idle stretch in a lane's entry list (job field)
+constexpr int32_t kIdleJob = 0x7FFF;    // codes stay positive; chain jobs are numbered below it
+constexpr int kMaxChainLength = 2048;      // jobs of one chain (their descriptors sit in LDS)
 
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
@@ -91,6 +96,25 @@ struct Plan {
     int32_t fused_waves = 0;
     LaneSchedule fused_lanes;
     bool fused_simple = false;
+    // Chain launch (kChainLaunch, or chosen by the cost model): chains of
+    // convolutions where each job's first operand is the previous job's output
+    // and its second an input series (p2's forward and backward products).
+    // Coefficient i of a product is final once its own i+1 terms are summed,
+    // and the next product of the chain reads its first operand in increasing
+    // i, so consecutive jobs of a chain overlap.  Layer L <= pipe_layers holds
+    // the jobs at position L of their chain; one launch runs them all, one
+    // workgroup of pipe_waves wavefronts per chain, with a workgroup barrier
+    // every pipe_window steps; layers after pipe_layers launch as usual.
+    // pipe_jobs: the chain jobs, chain after chain, in chain order;
+    // pipe_comps[c] = {first job, schedule code offset, stride, steps};
+    // pipe_codes: per schedule, 64 * pipe_waves rows of `stride` entries,
+    // (job << 16) | k for coefficient k of the chain's job (k+1 steps), or
+    // (kIdleJob << 16) | (g-1) for g idle steps, then -1.
+    int pipe_layers = 0;
+    int pipe_waves = 0, pipe_window = 0;
+    std::vector<std::array<int32_t, 3>> pipe_jobs;
+    std::vector<std::array<int32_t, 4>> pipe_comps;
+    std::vector<int32_t> pipe_codes;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };
@@ -121,5 +145,14 @@ int choose_jobs_per_group(int d, int w);
 // job spans several wavefronts; output slots are written.  Returns "" or
 // what is violated, naming the stage.
 std::string check_hazards(const Plan &P);
+
+// Chain launch schedule for one chain of L jobs of degree d on W wavefronts
+// with a barrier every S steps: codes (64W rows of *stride entries, the
+// encoding of Plan::pipe_codes).  Returns the steps (a multiple of S).
+int make_chain_schedule(int L, int d, int W, int S, std::vector<int32_t> &codes, int *stride);
+// Checks a chain schedule: every coefficient of every job exactly once, and
+// every first-operand read (issued two steps ahead of its use) after the
+// barrier that follows the store it reads.  Returns "" or what is wrong.
+std::string check_chain_schedule(int L, int d, int W, int S, int steps, const int32_t *codes, int stride);
 
 }  // namespace mdpe
