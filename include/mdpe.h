@@ -54,7 +54,8 @@ typedef struct {
     const int32_t *vars;    /* host [sum n_k]: 0-based variable indices, strictly
                                increasing inside each monomial (Section 4) */
     uint32_t flags;         /* 0, or MDPE_KEEP_MONOMIAL_VALUES, MDPE_COMPLEX, MDPE_STREAM_OPERANDS,
-                               MDPE_STAGE_OPERANDS, MDPE_ASAP_LAYERS */
+                               MDPE_STAGE_OPERANDS, MDPE_ASAP_LAYERS, MDPE_FUSED_LAYERS,
+                               MDPE_LAYER_LAUNCHES, MDPE_CHAIN_LAUNCH */
     const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
                                (every exponent one).  Monomial k is then
                                a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
@@ -131,9 +132,28 @@ typedef struct {
  * own schedule. */
 #define MDPE_FUSED_LAYERS 32u
 
-/* Plan flag: one launch per convolution layer, never fused (excludes
- * MDPE_FUSED_LAYERS). */
+/* Plan flag: one launch per convolution layer, never fused or chained
+ * (excludes MDPE_FUSED_LAYERS and MDPE_CHAIN_LAUNCH). */
 #define MDPE_LAYER_LAUNCHES 64u
+
+/* Plan flag: run the chains of products in one pipelined launch (plans do so
+ * by themselves where it is estimated well under the layered or fused
+ * launches: chains of at least 8 products holding a quarter of the
+ * convolutions or more, such as p2's).  A chain is a sequence of
+ * convolutions where each job's first operand is the previous job's output
+ * and its second a staged input series: the forward products f_j = f_{j-1} *
+ * z_{i_j} and the backward products b_j = b_{j-1} * z_{i_{n-j}} of Section 3.
+ * Coefficient i of a product is final once its own i+1 terms are summed, and
+ * the next product of its chain needs its first operand's coefficients in
+ * increasing i, so one workgroup per chain overlaps the chain's products,
+ * passing each coefficient on through LDS; the remaining convolutions (the
+ * cross products) follow in layers after it.  Each coefficient is the same
+ * sequential sum as in the per-layer launches, so every output bit is the
+ * same.  Such plans give the in-place product b_{n-2} * a_k a fresh output
+ * slot.  MDPE_EUNSUPPORTED when no chain qualifies or its first operands do
+ * not fit in LDS; excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES and
+ * MDPE_STREAM_OPERANDS. */
+#define MDPE_CHAIN_LAUNCH 128u
 
 /* Plan summary. */
 typedef struct {
@@ -160,6 +180,12 @@ typedef struct {
                                (0 when the layers are launched one by one) */
     int32_t fused_waves;    /* MDPE_FUSED_LAYERS: wavefronts per component workgroup (at most 4;
                                fewer at launch where their LDS would not fit) */
+    int32_t chain_layers;   /* MDPE_CHAIN_LAUNCH: layers 1..chain_layers run in the chain launch
+                               (layer L: the L-th product of every chain); 0 without it */
+    int32_t chain_count;    /* MDPE_CHAIN_LAUNCH: chains, one workgroup each */
+    int32_t chain_waves;    /* MDPE_CHAIN_LAUNCH: wavefronts per chain workgroup (4 or 8) */
+    int32_t chain_window;   /* MDPE_CHAIN_LAUNCH: steps between workgroup barriers */
+    int32_t chain_ring;     /* MDPE_CHAIN_LAUNCH: LDS slots of first operands per chain */
 } mdpe_plan_info;
 
 /*
@@ -190,6 +216,40 @@ int plan_conv_jobs(const mdpe_plan *plan, int32_t *rows);
  * fused launch runs them.  rows: int32[n_conv][5].  MDPE_EINVAL for a plan
  * without fused layers. */
 int plan_fused_jobs(const mdpe_plan *plan, int32_t *rows);
+
+/* MDPE_CHAIN_LAUNCH plans: the jobs of the chain launch as rows {chain,
+ * position in the chain (0-based), t1, t2, t3}, chain after chain; position q
+ * of every chain is convolution layer q+1.  rows: int32[n][5] with n the sum
+ * of the chain lengths (the jobs of layers 1..chain_layers).  MDPE_EINVAL for
+ * a plan without a chain launch. */
+int plan_chain_jobs(const mdpe_plan *plan, int32_t *rows);
+
+/*
+ * The lane schedule of one chain (host only): L products of degree d on
+ * `waves` wavefronts (4 or 8), a workgroup barrier every `window` steps, the
+ * first operands in `ring` LDS slots (job j's in slot j mod ring).  codes:
+ * int32[64 * waves][*stride], row r for thread r of the chain's workgroup:
+ * (j << 16) | k computes coefficient k of the j-th product (k+1 steps, its
+ * terms i = 0..k in increasing i), (0x7FFF << 16) | (g-1) idles g steps, -1
+ * ends the row.  *steps: steps every thread runs (a multiple of window).
+ * codes NULL returns only *stride and *steps; else capacity is its length.
+ */
+int chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t *codes,
+                   int64_t capacity, int32_t *stride, int32_t *steps);
+
+/*
+ * Check a chain schedule against the chain kernel's timing (host only):
+ * step t's first operand coefficient is read from LDS in iteration t-1 (step
+ * 0's before the loop), a coefficient is stored in the iteration of its last
+ * step, and a workgroup barrier follows iteration s when (s+1) % window == 0.
+ * Every coefficient of every product exactly once, within `steps`; each read
+ * of a first-operand coefficient in a later window than its store by the
+ * previous product, and its overwriting (by the product `ring` places later)
+ * in a later window than the read.  MDPE_OK, or MDPE_EINVAL with the first
+ * violation in last_error_string().
+ */
+int check_chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t steps,
+                         const int32_t *codes, int32_t stride);
 
 /* Addition jobs as rows {level (1-based), t1, t2}: A[t2] := A[t2] + A[t1].
  * rows: int32[n_add][3], in launch order. */

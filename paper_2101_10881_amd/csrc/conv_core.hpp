@@ -316,6 +316,150 @@ __global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A,
     }
 }
 
+// The chain launch.  Workgroup c runs chain c: products where each job's
+// first operand is the previous job's output and its second a staged input
+// series (the forward and backward products of Section 3).  Its lanes follow
+// the chain's schedule `codes` (rows of (job << 16) | k for coefficient k of
+// the chain's job-th product, k+1 steps; (kIdleJob << 16) | (g-1) for g idle
+// steps; -1 after the last): each coefficient is one lane's sequential sum of
+// its k+1 terms in the specified order, as in conv_group, so every bit is that
+// of the per-layer launches.  Job j's first operand sits in LDS slot j mod B:
+// job 0's is staged from A, every later job's is stored there coefficient by
+// coefficient by the job before it, beside its store to A.  Coefficient i of
+// a product is final after its own i+1 terms and the next product reads its
+// first operand in increasing i, so consecutive products overlap.  A
+// workgroup barrier after every S steps orders those LDS stores and reads: the
+// host checks that the schedule reads each coefficient only in a window after
+// that of its store, and overwrites a slot only in a window after that of its
+// last read (check_chain_schedule).  Second operands stream from A two steps
+// ahead; lanes without a coefficient compute on job 0's first terms and
+// store nothing.
+template <int M, bool CX, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void conv_chain_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                                const ChainComp *__restrict__ comps,
+                                                                const int *__restrict__ codes, int d, int B, int S) {
+    constexpr int W = kCoef<M, CX>;
+    extern __shared__ double lds[];
+    const ChainComp cc = comps[blockIdx.x];
+    const long SS = (long)(d + 1) * W;
+    double *ring = lds;
+    // per job: x = LDS offset of its first operand, y and z = offsets in A,
+    // unused = LDS offset of the next job's first operand (-1 for the last)
+    JobOffsets *jd = (JobOffsets *)((char *)lds + conv_lds_jobs_offset((long)B * SS));
+    const int tid = (int)threadIdx.x;
+    {
+        const int4 t0 = jobs[cc.first];
+        const double *xs = A + (long)t0.x * SS;
+        for (long q = tid; q < SS; q += 64 * WAVES) ring[q] = xs[q];
+        for (int j = tid; j < cc.len; j += 64 * WAVES) {
+            const int4 t = jobs[cc.first + j];
+            jd[j] = JobOffsets{(long)(j % B) * SS, (long)t.y * SS, (long)t.z * SS,
+                               j + 1 < cc.len ? (long)((j + 1) % B) * SS : -1L};
+        }
+    }
+    __syncthreads();
+
+    struct St {
+        const int *cp;  // the row entry after the current one (stays on the terminator)
+        int code, next, k, i;
+        bool live;      // a coefficient of a job (not idle, not past the row's end)
+        const double *x, *y;
+        double *out, *rout;
+    };
+    auto decode = [&](St &t) {
+        int j = 0;
+        if (t.code >= 0) {
+            j = t.code >> 16;
+            t.k = t.code & 0xffff;
+            t.live = j != kIdleJob;
+        } else {
+            t.k = 0;
+            t.live = false;
+        }
+        t.i = 0;
+        const JobOffsets &jb = jd[t.live ? j : 0];
+        const long kk = t.live ? t.k : 0;
+        t.x = ring + jb.x;
+        t.y = A + jb.y + kk * W;
+        t.out = A + jb.z + kk * W;
+        t.rout = jb.unused >= 0 ? ring + jb.unused + kk * W : nullptr;
+    };
+    auto advance = [&](const St &cur, St &nxt) {
+        nxt = cur;
+        if (cur.i == cur.k) {
+            nxt.code = cur.next;
+            if (nxt.code >= 0) ++nxt.cp;
+            nxt.next = *nxt.cp;
+            decode(nxt);
+        } else {
+            nxt.i = cur.i + 1;
+            if (cur.live) {
+                nxt.x += W;
+                nxt.y -= W;
+            }
+        }
+    };
+
+    const int *my = codes + cc.code_off + (long)tid * cc.stride;
+    St st;
+    st.code = my[0];
+    st.cp = my + (st.code >= 0 ? 1 : 0);
+    st.next = *st.cp;
+    decode(st);
+    double p[W];
+    {
+        double x0[W], y0[W];
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+            x0[l] = st.x[l];
+            y0[l] = st.y[l];
+        }
+        coef_mul<M, CX>(x0, y0, p);
+    }
+    St nx;
+    advance(st, nx);
+    double yn[W], acc[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) {
+        yn[l] = nx.y[l];
+        acc[l] = 0.0;
+    }
+    int until_barrier = S;
+    for (int s = 0; s < cc.steps; ++s) {
+        St n2;
+        advance(nx, n2);
+        double x1[W], y1[W];
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+            y1[l] = yn[l];
+            x1[l] = nx.x[l];
+            yn[l] = n2.y[l];
+        }
+        double pn[W], r[W];
+        coef_mul<M, CX>(x1, y1, pn);  // step s+1
+        coef_add<M, CX>(acc, p, r);   // step s; a coefficient's first term replaces acc
+        const bool first = st.i == 0;
+#pragma unroll
+        for (int l = 0; l < W; ++l) acc[l] = first ? p[l] : r[l];
+        if (st.i == st.k && st.live) {
+#pragma unroll
+            for (int l = 0; l < W; ++l) st.out[l] = acc[l];
+            if (st.rout) {
+#pragma unroll
+                for (int l = 0; l < W; ++l) st.rout[l] = acc[l];
+            }
+        }
+        st = nx;
+        nx = n2;
+#pragma unroll
+        for (int l = 0; l < W; ++l) p[l] = pn[l];
+        if (--until_barrier == 0) {
+            __syncthreads();
+            until_barrier = S;
+        }
+    }
+}
+
 // A[t2] := A[t2] + A[t1] at coefficient c (Section 5, the addition job).
 template <int M, bool CX = false>
 __device__ __forceinline__ void add_item(double *__restrict__ A, int2 t, int c, int d) {

@@ -224,6 +224,9 @@ void free_plan(mdpe_plan *p) {
         (void)hipFree(p->d_fconv);
         (void)hipFree(p->d_foff);
         (void)hipFree(p->d_fchains);
+        (void)hipFree(p->d_pjobs);
+        (void)hipFree(p->d_pcomps);
+        (void)hipFree(p->d_pcodes);
     }
     delete p;
 }
@@ -368,11 +371,47 @@ int launch_fused(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *
     return record(prof, 1, st, false);
 }
 
+// chain launch: one workgroup of pipe_waves wavefronts per chain
+template <int M, bool CX>
+int launch_chain(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    const long SS = (long)(P.d + 1) * mdpe::kCoef<M, CX>;
+    const size_t lds = (size_t)mdpe::conv_lds_jobs_offset((long)P.pipe_ring * SS) +
+                       (size_t)P.pipe_layers * sizeof(mdpe::JobOffsets);
+    if (lds > (size_t)mdpe::kMaxLdsBytes) return fail(MDPE_EUNSUPPORTED, "chain launch: LDS beyond one workgroup's");
+    static std::atomic<bool> attr_set[kMaxDevices];
+    const int dv = pl->device >= 0 && pl->device < kMaxDevices ? pl->device : 0;
+    if (!attr_set[dv].load()) {
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_chain_kernel<M, CX, 4>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_chain_kernel<M, CX, 8>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        attr_set[dv].store(true);
+    }
+    const unsigned chains = (unsigned)P.pipe_comps.size();
+    int rc = record(prof, 1, st, true);
+    if (rc) return rc;
+    if (P.pipe_waves == 4)
+        hipLaunchKernelGGL((mdpe::conv_chain_kernel<M, CX, 4>), dim3(chains), dim3(256), lds, st, A, pl->d_pjobs,
+                           pl->d_pcomps, pl->d_pcodes, P.d, P.pipe_ring, P.pipe_window);
+    else if (P.pipe_waves == 8)
+        hipLaunchKernelGGL((mdpe::conv_chain_kernel<M, CX, 8>), dim3(chains), dim3(512), lds, st, A, pl->d_pjobs,
+                           pl->d_pcomps, pl->d_pcodes, P.d, P.pipe_ring, P.pipe_window);
+    else
+        return fail(MDPE_EUNSUPPORTED, "chain launch: 4 or 8 wavefronts per chain");
+    LAUNCH_CHECK("conv_chain_kernel");
+    return record(prof, 1, st, false);
+}
+
 template <int M, bool CX>
 int launch_conv(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     const mdpe::Plan &P = pl->P;
     if (P.fused_components > 0) return launch_fused<M, CX>(pl, A, st, prof);
-    for (int L = 1; L <= P.n_layers(); ++L) {
+    if (P.pipe_layers > 0) {
+        int rc = launch_chain<M, CX>(pl, A, st, prof);
+        if (rc) return rc;
+    }
+    for (int L = P.pipe_layers + 1; L <= P.n_layers(); ++L) {
         const long off = P.conv_off[L - 1];
         int rc = launch_layer<M, false, CX>(pl, A, pl->d_conv + off, (int)(P.conv_off[L] - off), st, prof);
         if (rc) return rc;
@@ -537,7 +576,7 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
     if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS |
-                                MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES))
+                                MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES | MDPE_CHAIN_LAUNCH))
         return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
@@ -568,6 +607,9 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
         std::vector<int4> fconv(P.fused_conv.size());
         for (size_t q = 0; q < P.fused_conv.size(); ++q)
             fconv[q] = make_int4(P.fused_conv[q][0], P.fused_conv[q][1], P.fused_conv[q][2], 0);
+        std::vector<int4> pjobs(P.pipe_jobs.size());
+        for (size_t q = 0; q < P.pipe_jobs.size(); ++q)
+            pjobs[q] = make_int4(P.pipe_jobs[q][0], P.pipe_jobs[q][1], P.pipe_jobs[q][2], 0);
         std::vector<int2> add(P.add.size()), stage(P.stage.size());
         for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
         for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
@@ -585,7 +627,10 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
             (rc = upload(&raw->d_scale, scale.data(), scale.size() * sizeof(int4))) ||
             (rc = upload(&raw->d_fconv, fconv.data(), fconv.size() * sizeof(int4))) ||
             (rc = upload(&raw->d_foff, P.fused_off.data(), P.fused_off.size() * sizeof(int))) ||
-            (rc = upload(&raw->d_fchains, P.fused_lanes.chains.data(), P.fused_lanes.chains.size() * sizeof(int)))) {
+            (rc = upload(&raw->d_fchains, P.fused_lanes.chains.data(), P.fused_lanes.chains.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_pjobs, pjobs.data(), pjobs.size() * sizeof(int4))) ||
+            (rc = upload(&raw->d_pcomps, P.pipe_comps.data(), P.pipe_comps.size() * sizeof(mdpe::ChainComp))) ||
+            (rc = upload(&raw->d_pcodes, P.pipe_codes.data(), P.pipe_codes.size() * sizeof(int)))) {
             std::string keep = g_err;
             free_plan(pl.release());
             g_err = keep;
@@ -615,6 +660,11 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->balanced_layers = P.balanced ? 1 : 0;
     o->fused_components = P.fused_components;
     o->fused_waves = P.fused_waves;
+    o->chain_layers = P.pipe_layers;
+    o->chain_count = (int32_t)P.pipe_comps.size();
+    o->chain_waves = P.pipe_waves;
+    o->chain_window = P.pipe_window;
+    o->chain_ring = P.pipe_ring;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;
@@ -777,6 +827,57 @@ int plan_reverse_jobs(const mdpe_plan *pl, int32_t *rows) {
     const mdpe::Plan &P = pl->P;
     for (size_t q = 0; q < P.corr.size(); ++q)
         for (int r = 0; r < 3; ++r) rows[3 * q + r] = P.corr[q][r];
+    return MDPE_OK;
+}
+
+int plan_chain_jobs(const mdpe_plan *pl, int32_t *rows) {
+    if (!pl || !rows) return fail(MDPE_EINVAL, "plan and rows are required");
+    const mdpe::Plan &P = pl->P;
+    if (P.pipe_layers == 0) return fail(MDPE_EINVAL, "the plan has no chain launch (MDPE_CHAIN_LAUNCH)");
+    for (size_t c = 0; c < P.pipe_comps.size(); ++c) {
+        const mdpe::ChainComp &cc = P.pipe_comps[c];
+        for (int32_t q = 0; q < cc.len; ++q) {
+            const auto &t = P.pipe_jobs[(size_t)cc.first + q];
+            int32_t *r = rows + 5 * ((size_t)cc.first + q);
+            r[0] = (int32_t)c;
+            r[1] = q;
+            r[2] = t[0];
+            r[3] = t[1];
+            r[4] = t[2];
+        }
+    }
+    return MDPE_OK;
+}
+
+int chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t *codes,
+                   int64_t capacity, int32_t *stride, int32_t *steps) {
+    if (L < 1 || L > mdpe::kMaxChainLength || d < 0 || d > 4095 || (waves != 4 && waves != 8) || window < 1 ||
+        ring < 2 || !stride || !steps || capacity < 0)
+        return fail(MDPE_EINVAL, "need 1 <= L <= 2048, 0 <= d <= 4095, waves 4 or 8, window >= 1, ring >= 2");
+    std::vector<int32_t> cs;
+    int st = 0;
+    try {
+        *steps = mdpe::make_chain_schedule(L, d, waves, window, ring, cs, &st);
+    } catch (const std::bad_alloc &) {
+        return fail(MDPE_ENOMEM, "host allocation failed");
+    }
+    *stride = st;
+    if (codes) {
+        if ((int64_t)cs.size() > capacity) return fail(MDPE_EINVAL, "codes: capacity below 64 * waves * stride");
+        std::memcpy(codes, cs.data(), cs.size() * sizeof(int32_t));
+    }
+    return MDPE_OK;
+}
+
+int check_chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t steps,
+                         const int32_t *codes, int32_t stride) {
+    std::string e;
+    try {
+        e = mdpe::check_chain_schedule(L, d, waves, window, ring, steps, codes, stride);
+    } catch (const std::bad_alloc &) {
+        return fail(MDPE_ENOMEM, "host allocation failed");
+    }
+    if (!e.empty()) return fail(MDPE_EINVAL, e);
     return MDPE_OK;
 }
 

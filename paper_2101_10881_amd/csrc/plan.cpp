@@ -516,6 +516,265 @@ static bool fuse_by_default(const Plan &P) {
     return P.d <= (P.w <= 4 ? 127 : (P.w == 5 || P.w == 10) ? 31 : 8);
 }
 
+// ------------------------------------------------------------ chain launch
+// Timing of the chain kernel (conv_chain_kernel): every lane of a chain's
+// workgroup runs the same steps.  The first operand of step t is read from
+// LDS in iteration t-1 (in the prologue, iteration -1, for t = 0); a
+// coefficient is stored -- to A and, for the chain's next product, to the LDS
+// slot of that product's first operand -- in the iteration of its last step;
+// a workgroup barrier follows iteration s when (s+1) % S == 0.  A store and a
+// read of one LDS coefficient are therefore ordered exactly when their
+// windows floor(iteration / S) differ.
+
+static inline int chain_window(int it, int S) { return it >= 0 ? it / S : -1; }
+
+int make_chain_schedule(int L, int d, int W, int S, int B, std::vector<int32_t> &codes, int *stride) {
+    // Jobs in chain order, each job's coefficients longest first; each at the
+    // earliest step its first operand allows (every x_i read after the window
+    // of its store by the previous job; its own store into the LDS slot of
+    // job l+1 after the last read of the product that slot held, B jobs
+    // earlier), on the lane free by then with the least idle time before it,
+    // else on the lane that frees first.
+    const int lanes = kLanes * W, d1 = d + 1;
+    std::vector<int> lane_free(lanes, 0);
+    std::vector<std::vector<int32_t>> lists(lanes);
+    std::vector<int> store((size_t)L * d1, 0);
+    std::vector<int> last_read(L, -1);
+    for (int l = 0; l < L; ++l) {
+        for (int k = d; k >= 0; --k) {
+            int s0 = 0;
+            if (l > 0)
+                for (int i = 0; i <= k; ++i)
+                    s0 = std::max(s0, S * (chain_window(store[(size_t)(l - 1) * d1 + i], S) + 1) - i + 1);
+            if (l + 1 < L && l + 1 - B >= 0) s0 = std::max(s0, S * (chain_window(last_read[l + 1 - B], S) + 1) - k);
+            int best = -1;
+            for (int q = 0; q < lanes; ++q)
+                if (lane_free[q] <= s0 && (best < 0 || lane_free[q] > lane_free[best])) best = q;
+            if (best < 0) {
+                best = 0;
+                for (int q = 1; q < lanes; ++q)
+                    if (lane_free[q] < lane_free[best]) best = q;
+            }
+            const int start = std::max(s0, lane_free[best]);
+            for (int g = start - lane_free[best]; g > 0;) {
+                const int q = std::min(g, 0x10000);
+                lists[best].push_back((kIdleJob << 16) | (q - 1));
+                g -= q;
+            }
+            lists[best].push_back((l << 16) | k);
+            lane_free[best] = start + k + 1;
+            store[(size_t)l * d1 + k] = start + k;
+            last_read[l] = std::max(last_read[l], start + k - 1);
+        }
+    }
+    int steps = *std::max_element(lane_free.begin(), lane_free.end());
+    steps = (steps + S - 1) / S * S;
+    size_t st = 1;
+    for (auto &x : lists) st = std::max(st, x.size() + 1);
+    *stride = (int)st;
+    codes.assign((size_t)lanes * st, -1);
+    for (int q = 0; q < lanes; ++q) std::copy(lists[q].begin(), lists[q].end(), codes.begin() + (size_t)q * st);
+    return steps;
+}
+
+std::string check_chain_schedule(int L, int d, int W, int S, int B, int steps, const int32_t *codes, int stride) {
+    if (L < 1 || L > kMaxChainLength || d < 0 || W < 1 || W > 16 || S < 1 || B < 2 || steps < 0 || steps % S ||
+        stride < 1 || !codes)
+        return "bad chain schedule parameters";
+    const int lanes = kLanes * W, d1 = d + 1;
+    std::vector<int> start((size_t)L * d1, -1);
+    for (int q = 0; q < lanes; ++q) {
+        const int32_t *row = codes + (size_t)q * stride;
+        long t = 0;
+        int e = 0;
+        for (; e < stride && row[e] >= 0; ++e) {
+            const int j = row[e] >> 16, k = row[e] & 0xffff;
+            if (j == kIdleJob) {
+                t += k + 1;
+                continue;
+            }
+            if (j >= L || k > d) return "code out of range";
+            const size_t key = (size_t)j * d1 + k;
+            if (start[key] >= 0) return "coefficient scheduled twice";
+            start[key] = (int)t;
+            t += k + 1;
+        }
+        if (e == stride) return "row without its terminator";
+        if (t > steps) return "row longer than the steps";
+    }
+    for (int v : start)
+        if (v < 0) return "coefficient never scheduled";
+    for (int l = 0; l < L; ++l)
+        for (int k = 0; k <= d; ++k) {
+            const int s = start[(size_t)l * d1 + k];
+            for (int i = 0; i <= k; ++i) {
+                const int rd = s + i - 1;  // iteration that reads x_i
+                // job 0's first operand is staged before the first barrier
+                if (l > 0 && chain_window(rd, S) <= chain_window(start[(size_t)(l - 1) * d1 + i] + i, S))
+                    return "job " + std::to_string(l) + " coefficient " + std::to_string(k) +
+                           ": first operand read before the barrier after its store";
+                // job l-1+B stores the first operand of job l+B into the same slot
+                const int wj = l - 1 + B;
+                if (wj + 1 < L && chain_window(start[(size_t)wj * d1 + i] + i, S) <= chain_window(rd, S))
+                    return "job " + std::to_string(l) + " coefficient " + std::to_string(k) +
+                           ": first operand overwritten before the barrier after its read";
+            }
+        }
+    return "";
+}
+
+// Chains of the plan's convolutions: a job whose second operand is a staged
+// input (written by no convolution) starts a chain when its first operand is
+// one too, and continues the chain of its first operand's writer when it is
+// the first such job to read that output.  Jobs in launch (topological)
+// order; chains[c] lists job indices in chain order.  Requires one writer per
+// slot (no in-place jobs).
+static bool find_chains(const Plan &P, std::vector<std::vector<int64_t>> &chains) {
+    const size_t nj = P.conv.size();
+    std::vector<int64_t> writer(P.n_series, -1);
+    for (size_t j = 0; j < nj; ++j) {
+        if (writer[P.conv[j][2]] >= 0) return false;
+        writer[P.conv[j][2]] = (int64_t)j;
+    }
+    std::vector<int64_t> chain_of(nj, -1);
+    chains.clear();
+    for (size_t j = 0; j < nj; ++j) {
+        const auto &t = P.conv[j];
+        if (writer[t[1]] >= 0 || t[0] == t[2]) continue;
+        const int64_t p = writer[t[0]];
+        if (p < 0) {
+            chain_of[j] = (int64_t)chains.size();
+            chains.push_back({(int64_t)j});
+        } else if (chain_of[p] >= 0 && chains[chain_of[p]].back() == p &&
+                   (int)chains[chain_of[p]].size() < kMaxChainLength) {
+            chain_of[j] = chain_of[p];
+            chains[chain_of[p]].push_back((int64_t)j);
+        }
+    }
+    return !chains.empty();
+}
+
+// Rebuilds P's convolution layers for the chain launch with W wavefronts per
+// chain, a barrier every S steps and B LDS slots of first operands: layer L
+// <= pipe_layers holds the jobs at position L of their chain, the other jobs
+// follow at their earliest layers.  Returns the estimated cost (in wavefront
+// steps per SIMD, the unit of layer_cost) or -1 when no chain launch applies.
+static double make_chain_plan(Plan &P, const std::vector<std::vector<int64_t>> &chains, int W, int S, int B) {
+    const size_t nj = P.conv.size();
+    int Lmax = 0;
+    std::vector<char> in_chain(nj, 0);
+    for (auto &c : chains) {
+        Lmax = std::max(Lmax, (int)c.size());
+        for (int64_t j : c) in_chain[j] = 1;
+    }
+    // the other jobs at their earliest layers after the chain launch
+    std::vector<int> wlayer(P.n_series, 0);
+    std::vector<int> rest_layer(nj, 0);
+    int rest_layers = 0;
+    for (size_t j = 0; j < nj; ++j) {
+        if (in_chain[j]) continue;
+        const auto &t = P.conv[j];
+        const int L = std::max(wlayer[t[0]], wlayer[t[1]]) + 1;
+        rest_layer[j] = L;
+        wlayer[t[2]] = std::max(wlayer[t[2]], L);
+        rest_layers = std::max(rest_layers, L);
+    }
+    std::vector<std::array<int32_t, 3>> conv;
+    std::vector<int64_t> off{0};
+    for (int L = 0; L < Lmax; ++L) {
+        for (auto &c : chains)
+            if ((int)c.size() > L) conv.push_back(P.conv[c[L]]);
+        off.push_back((int64_t)conv.size());
+    }
+    for (int L = 1; L <= rest_layers; ++L) {
+        for (size_t j = 0; j < nj; ++j)
+            if (!in_chain[j] && rest_layer[j] == L) conv.push_back(P.conv[j]);
+        off.push_back((int64_t)conv.size());
+    }
+    if (conv.size() != nj) return -1;
+    // one schedule per chain length
+    std::vector<ChainComp> comps;
+    std::vector<std::array<int32_t, 3>> pjobs;
+    std::vector<int32_t> codes;
+    std::vector<std::array<int, 3>> sched(Lmax + 1, {-1, 0, 0});  // length -> {code_off, stride, steps}
+    int worst = 0;
+    for (auto &c : chains) {
+        const int len = (int)c.size();
+        if (sched[len][0] < 0) {
+            std::vector<int32_t> cs;
+            int stride = 0;
+            const int steps = make_chain_schedule(len, P.d, W, S, B, cs, &stride);
+            if (!check_chain_schedule(len, P.d, W, S, B, steps, cs.data(), stride).empty()) return -1;
+            if (codes.size() + cs.size() > (size_t)INT32_MAX / 2) return -1;
+            sched[len] = {(int)codes.size(), stride, steps};
+            codes.insert(codes.end(), cs.begin(), cs.end());
+        }
+        comps.push_back(ChainComp{(int32_t)pjobs.size(), len, sched[len][0], sched[len][1], sched[len][2], 0, 0, 0});
+        worst = std::max(worst, sched[len][2]);
+        for (int64_t j : c) pjobs.push_back(P.conv[j]);
+    }
+    P.conv.swap(conv);
+    P.conv_off.swap(off);
+    P.pipe_layers = Lmax;
+    P.pipe_waves = W;
+    P.pipe_window = S;
+    P.pipe_ring = B;
+    P.pipe_jobs.swap(pjobs);
+    P.pipe_comps.swap(comps);
+    P.pipe_codes.swap(codes);
+    P.balanced = false;
+    choose_staged_lanes(P, Lmax + 1);
+    // a chain's workgroup holds a CU: W/4 wavefronts per SIMD, ceil(chains / CUs) rounds
+    const long cus = kSimds / 4;
+    const double rounds = std::ceil((double)chains.size() / cus);
+    const double chain_cost = rounds * worst * std::max(1.0, W / 4.0) * (1.0 + 0.02 * 4.0 / S);
+    return chain_cost + layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0, Lmax + 1);
+}
+
+// LDS slots of first operands a chain workgroup gets: up to 96 KiB of LDS
+// (one workgroup per CU then), at least two, at most the longest chain.
+static int chain_ring_slots(const Plan &P, int Lmax) {
+    const long per = (long)(P.d + 1) * P.w * 8;
+    const long jobs = (long)Lmax * 32;
+    const long fit = (98304 - jobs) / per;
+    return (int)std::min<long>(std::max(Lmax, 2), fit);
+}
+
+// The chain launch for a plan without in-place jobs: the cheapest of W = 4,
+// 8 wavefronts and barriers every S = 1, 2, 4 steps, applied when forced or
+// estimated under 0.6 of `other` (the cost of the plan without it).  Returns
+// whether P now holds a chain launch.
+static constexpr bool kChainByDefault = false;
+
+static bool choose_chain_launch(Plan &P, bool forced, double other) {
+    if (P.streamed) return false;
+    std::vector<std::vector<int64_t>> chains;
+    if (!find_chains(P, chains)) return false;
+    int Lmax = 0;
+    long members = 0;
+    for (auto &c : chains) {
+        Lmax = std::max(Lmax, (int)c.size());
+        members += (long)c.size();
+    }
+    if (!forced && (Lmax < 8 || 4 * members < (long)P.conv.size())) return false;
+    const int B = chain_ring_slots(P, Lmax);
+    if (B < 2) return false;
+    double best = -1;
+    int bw = 0, bs = 0;
+    for (int W : {4, 8})
+        for (int S : {1, 2, 4}) {
+            Plan T = P;
+            const double c = make_chain_plan(T, chains, W, S, B);
+            if (c >= 0 && (best < 0 || c < best)) {
+                best = c;
+                bw = W;
+                bs = S;
+            }
+        }
+    if (best < 0 || (!forced && best >= 0.6 * other)) return false;
+    return make_chain_plan(P, chains, bw, bs, B) >= 0;
+}
+
 std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
                        uint32_t flags, Plan &P, bool *unsupported) {
     // Staged operands unless asked otherwise, or unless they do not fit in
@@ -523,6 +782,28 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     // to be faster (large d with few jobs per layer).
     std::string err = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, false, P, unsupported);
     if (!err.empty()) return err;
+    // The chain launch (deep chains of products, p2's above all), when asked
+    // for or estimated well under the layered or fused plan.  Its plans give
+    // the in-place products fresh output slots: a chain's products overlap,
+    // so b_{n-2} must stay readable while b_{n-2} * a_k is stored.
+    const bool chain_forced = (flags & kChainLaunch) != 0;
+    if (!P.streamed && !(flags & (kFusedLayers | kLayerLaunches)) && (chain_forced || (kChainByDefault && P.n_layers() >= 8))) {
+        double other = layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0);
+        if (fuse_by_default(P)) other = std::min(other, (double)P.n_layers() * make_lane_schedule(d, 1).steps);
+        Plan C;
+        bool uns = false;
+        std::string e2 = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, true, C, &uns);
+        if (e2.empty() && choose_chain_launch(C, chain_forced, other)) {
+            auto h = check_hazards(C);
+            if (!h.empty()) return "internal planner error (chain launch): " + h;
+            P = std::move(C);
+            return "";
+        }
+    }
+    if (chain_forced) {
+        *unsupported = true;
+        return "MDPE_CHAIN_LAUNCH: no chain of products to pipeline, or its first operands do not fit in LDS";
+    }
     auto fuse = [&]() {
         if (P.streamed) return err;
         if (flags & kFusedLayers)
@@ -547,8 +828,10 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
                                    bool *unsupported) {
     *unsupported = false;
     if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers | kFusedLayers |
-                  kLayerLaunches))
+                  kLayerLaunches | kChainLaunch))
         return "unknown flags";
+    if ((flags & kChainLaunch) && (flags & (kFusedLayers | kLayerLaunches | kStreamOperands)))
+        return "MDPE_CHAIN_LAUNCH excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES and MDPE_STREAM_OPERANDS";
     if ((flags & kFusedLayers) && (flags & kLayerLaunches)) return "MDPE_FUSED_LAYERS and MDPE_LAYER_LAUNCHES exclude each other";
     if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;

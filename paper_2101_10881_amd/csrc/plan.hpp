@@ -48,6 +48,13 @@ constexpr uint32_t kChainLaunch = 128u;    // first-operand chains in one pipeli
 constexpr int32_t kIdleJob = 0x7FFF;    // codes stay positive; chain jobs are numbered below it
 constexpr int kMaxChainLength = 2048;      // jobs of one chain (their descriptors sit in LDS)
 
+// One chain of the chain launch: its jobs pipe_jobs[first .. first+len), its
+// lane schedule at pipe_codes[code_off], `stride` entries per row, `steps`
+// steps (a multiple of the barrier window).
+struct ChainComp {
+    int32_t first, len, code_off, stride, steps, pad0, pad1, pad2;
+};
+
 struct Plan {
     int n = 0, N = 0, d = 0, m = 0;
     int w = 0;                         // doubles per coefficient: m, or 2m for complex series
@@ -97,23 +104,26 @@ struct Plan {
     LaneSchedule fused_lanes;
     bool fused_simple = false;
     // Chain launch (kChainLaunch, or chosen by the cost model): chains of
-    // convolutions where each job's first operand is the previous job's output
-    // and its second an input series (p2's forward and backward products).
-    // Coefficient i of a product is final once its own i+1 terms are summed,
-    // and the next product of the chain reads its first operand in increasing
-    // i, so consecutive jobs of a chain overlap.  Layer L <= pipe_layers holds
-    // the jobs at position L of their chain; one launch runs them all, one
-    // workgroup of pipe_waves wavefronts per chain, with a workgroup barrier
-    // every pipe_window steps; layers after pipe_layers launch as usual.
-    // pipe_jobs: the chain jobs, chain after chain, in chain order;
-    // pipe_comps[c] = {first job, schedule code offset, stride, steps};
-    // pipe_codes: per schedule, 64 * pipe_waves rows of `stride` entries,
-    // (job << 16) | k for coefficient k of the chain's job (k+1 steps), or
-    // (kIdleJob << 16) | (g-1) for g idle steps, then -1.
+    // convolutions where each job's first operand is the previous job's
+    // output and its second a staged input series (p2's forward and backward
+    // products).  Coefficient i of a product is final once its own i+1 terms
+    // are summed, and the next product of the chain reads its first operand
+    // in increasing i, so consecutive jobs of a chain overlap.  Layer
+    // L <= pipe_layers holds the jobs at position L of their chain; one
+    // launch runs them all, one workgroup of pipe_waves wavefronts per chain,
+    // with a workgroup barrier every pipe_window steps; the layers after
+    // pipe_layers launch one by one.
+    // pipe_jobs: the chain jobs {t1, t2, t3}, chain after chain, in chain order;
+    // pipe_comps: one per chain;
+    // pipe_codes: per schedule (chains of one length share one), 64 *
+    // pipe_waves rows of `stride` entries: (job << 16) | k for coefficient k
+    // of the chain's job-th product (k+1 steps), or (kIdleJob << 16) | (g-1)
+    // for g idle steps, then -1.
+    // pipe_ring: LDS slots of first operands per chain (job j's in slot j mod pipe_ring).
     int pipe_layers = 0;
-    int pipe_waves = 0, pipe_window = 0;
+    int pipe_waves = 0, pipe_window = 0, pipe_ring = 0;
     std::vector<std::array<int32_t, 3>> pipe_jobs;
-    std::vector<std::array<int32_t, 4>> pipe_comps;
+    std::vector<ChainComp> pipe_comps;
     std::vector<int32_t> pipe_codes;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
@@ -147,12 +157,18 @@ int choose_jobs_per_group(int d, int w);
 std::string check_hazards(const Plan &P);
 
 // Chain launch schedule for one chain of L jobs of degree d on W wavefronts
-// with a barrier every S steps: codes (64W rows of *stride entries, the
-// encoding of Plan::pipe_codes).  Returns the steps (a multiple of S).
-int make_chain_schedule(int L, int d, int W, int S, std::vector<int32_t> &codes, int *stride);
-// Checks a chain schedule: every coefficient of every job exactly once, and
-// every first-operand read (issued two steps ahead of its use) after the
-// barrier that follows the store it reads.  Returns "" or what is wrong.
-std::string check_chain_schedule(int L, int d, int W, int S, int steps, const int32_t *codes, int stride);
+// with a workgroup barrier every S steps and first operands in B LDS slots:
+// codes (64W rows of *stride entries, the encoding of Plan::pipe_codes).
+// Returns the steps (a multiple of S).
+int make_chain_schedule(int L, int d, int W, int S, int B, std::vector<int32_t> &codes, int *stride);
+// Checks a chain schedule against the kernel's timing: every coefficient of
+// every job exactly once, within `steps`; the first operand of step t is read
+// from LDS in iteration t-1 (the prologue, iteration -1, for step 0), a
+// coefficient's result is stored in the iteration of its last step, and a
+// barrier follows every iteration s with (s+1) % S == 0.  Every read of a
+// job's first operand must come after the barrier that follows the store of
+// that coefficient by the previous job, and before the barrier that precedes
+// its overwriting (B slots later).  Returns "" or what is wrong.
+std::string check_chain_schedule(int L, int d, int W, int S, int B, int steps, const int32_t *codes, int stride);
 
 }  // namespace mdpe

@@ -29,6 +29,9 @@ struct mdpe_plan {
     int4 *d_fconv = nullptr;   // fused layers: jobs by component, then layer
     int *d_foff = nullptr;     // fused layers: per-component layer offsets
     int *d_fchains = nullptr;  // fused layers: the one-job lane schedule
+    int4 *d_pjobs = nullptr;   // chain launch: jobs chain after chain
+    mdpe::ChainComp *d_pcomps = nullptr;  // chain launch: one per chain
+    int *d_pcodes = nullptr;   // chain launch: lane schedules
 };
 
 namespace mdpe {

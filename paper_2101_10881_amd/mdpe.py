@@ -27,6 +27,7 @@ MDPE_STAGE_OPERANDS = 8
 MDPE_ASAP_LAYERS = 16
 MDPE_FUSED_LAYERS = 32
 MDPE_LAYER_LAUNCHES = 64
+MDPE_CHAIN_LAUNCH = 128
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -50,7 +51,9 @@ class PlanInfo(ctypes.Structure):
                 ("n_reverse", ctypes.c_int64), ("flags", ctypes.c_uint32), ("n_scale", ctypes.c_int64),
                 ("waves_per_job", ctypes.c_int32), ("streamed", ctypes.c_int32),
                 ("simple_dealing", ctypes.c_int32), ("balanced_layers", ctypes.c_int32),
-                ("fused_components", ctypes.c_int32), ("fused_waves", ctypes.c_int32)]
+                ("fused_components", ctypes.c_int32), ("fused_waves", ctypes.c_int32),
+                ("chain_layers", ctypes.c_int32), ("chain_count", ctypes.c_int32), ("chain_waves", ctypes.c_int32),
+                ("chain_window", ctypes.c_int32), ("chain_ring", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,6 +101,9 @@ def lib():
     L.plan_layer_sizes.argtypes = [_vp, _i32p, _i32p]
     L.plan_conv_jobs.argtypes = [_vp, _i32p]
     L.plan_fused_jobs.argtypes = [_vp, _i32p]
+    L.plan_chain_jobs.argtypes = [_vp, _i32p]
+    L.chain_schedule.argtypes = [ctypes.c_int32] * 5 + [_i32p, ctypes.c_int64, _i32p, _i32p]
+    L.check_chain_schedule.argtypes = [ctypes.c_int32] * 6 + [_i32p, ctypes.c_int32]
     L.plan_add_jobs.argtypes = [_vp, _i32p]
     L.plan_outputs.argtypes = [_vp, _i32p]
     L.plan_scale_jobs.argtypes = [_vp, _i32p]
@@ -225,6 +231,13 @@ class Plan:
         _check(lib().plan_fused_jobs(self._h, rows.ctypes.data_as(_i32p)))
         return rows[: self.info["n_conv"]]
 
+    def chain_jobs(self):
+        """MDPE_CHAIN_LAUNCH plans: rows {chain, position, t1, t2, t3}, chain after chain."""
+        n = int(sum(self.layer_sizes()[0][: self.info["chain_layers"]]))
+        rows = np.zeros((max(n, 1), 5), dtype=np.int32)
+        _check(lib().plan_chain_jobs(self._h, rows.ctypes.data_as(_i32p)))
+        return rows[:n]
+
     def add_jobs(self):
         rows = np.zeros((max(self.info["n_add"], 1), 3), dtype=np.int32)
         _check(lib().plan_add_jobs(self._h, rows.ctypes.data_as(_i32p)))
@@ -257,6 +270,24 @@ def check_plan_jobs(n, N, n_series, conv_rows, add_rows, out_slots=None, extra_s
                                  out.ctypes.data_as(_i32p) if out is not None else None,
                                  extra.ctypes.data_as(_i32p) if extra.size else None, int(extra.size),
                                  int(waves_per_job), int(bool(streamed))))
+
+
+def chain_schedule(L, d, waves, window, ring):
+    """Host-only lane schedule of one chain: (codes int32[64*waves][stride], steps)."""
+    stride, steps = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().chain_schedule(int(L), int(d), int(waves), int(window), int(ring), None, 0, ctypes.byref(stride),
+                                ctypes.byref(steps)))
+    codes = np.zeros((64 * int(waves), stride.value), dtype=np.int32)
+    _check(lib().chain_schedule(int(L), int(d), int(waves), int(window), int(ring), codes.ctypes.data_as(_i32p),
+                                int(codes.size), ctypes.byref(stride), ctypes.byref(steps)))
+    return codes, steps.value
+
+
+def check_chain_schedule(L, d, waves, window, ring, steps, codes):
+    """Raise MdpeError unless `codes` meets the chain kernel's ordering rules."""
+    codes = np.ascontiguousarray(codes, dtype=np.int32)
+    _check(lib().check_chain_schedule(int(L), int(d), int(waves), int(window), int(ring), int(steps),
+                                      codes.ctypes.data_as(_i32p), int(codes.shape[1])))
 
 
 def plan_polynomial(n, nvars, vars_, d, m, device=0) -> Plan:
@@ -337,11 +368,15 @@ class Polynomial:
     stream_operands / fused_layers: None lets the plan choose; True / False
     forces operands read from global memory (else staged in LDS) / every
     convolution layer in one launch (else one launch per layer).
+    chain_launch: True forces the chains of products into one pipelined
+    launch (MDPE_CHAIN_LAUNCH); None lets the plan choose; fused_layers=False
+    excludes it too.
     asap_layers: every convolution at its earliest layer (no balancing).
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
-                 stream_operands=None, asap_layers=False, fused_layers=None, alloc_workspace=True):
+                 stream_operands=None, asap_layers=False, fused_layers=None, alloc_workspace=True,
+                 chain_launch=None):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
@@ -353,7 +388,8 @@ class Polynomial:
                  (MDPE_ASAP_LAYERS if asap_layers else 0) |
                  # fused_layers: None lets the plan choose, True / False forces it
                  (MDPE_FUSED_LAYERS if fused_layers is True else 0) |
-                 (MDPE_LAYER_LAUNCHES if fused_layers is False else 0))
+                 (MDPE_LAYER_LAUNCHES if fused_layers is False else 0) |
+                 (MDPE_CHAIN_LAUNCH if chain_launch is True else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)
@@ -366,9 +402,10 @@ class Polynomial:
 
     @classmethod
     def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False,
-                     fused_layers=None, alloc_workspace=True):
+                     fused_layers=None, alloc_workspace=True, chain_launch=None):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
-                   getattr(w, "exps", None), stream_operands, asap_layers, fused_layers, alloc_workspace)
+                   getattr(w, "exps", None), stream_operands, asap_layers, fused_layers, alloc_workspace,
+                   chain_launch)
 
     def new_workspace(self):
         import torch

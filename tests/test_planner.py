@@ -249,7 +249,9 @@ def test_complex_plan_same_jobs_double_workspace():
 
 @pytest.mark.parametrize("flags, m, d, code", [
     (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
-    (128, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
+    (256, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
+    (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_FUSED_LAYERS, 2, 3, mdpe.MDPE_EINVAL),
+    (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_STREAM_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_STREAM_OPERANDS | mdpe.MDPE_STAGE_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_STAGE_OPERANDS, 10, 1700, mdpe.MDPE_EUNSUPPORTED),  # does not fit in LDS
 ])
