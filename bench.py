@@ -39,7 +39,7 @@ def parse():
                     help="run one torch copy of this size before timing (for HBM counter calibration)")
     ap.add_argument("--no-check", dest="check", action="store_false",
                     help="skip comparing the output digest with the oracle's (compared by default)")
-    ap.add_argument("--workload", default="p1", choices=["p1", "batch", "sweep"],
+    ap.add_argument("--workload", default="p1", choices=["p1", "batch", "sweep", "rand3", "p2", "autograd"],
                     help="p1: deca double d=152 (the headline); batch: 512 mixed instances vs separate launches; "
                          "sweep: the paper's precision x degree tables for p1, p2, p3")
     ap.add_argument("--polys", default="p1,p2,p3", help="sweep: test polynomials")
@@ -176,7 +176,7 @@ def _bits_equal(gpu, want):
     return bool(np.array_equal(g, np.ascontiguousarray(want, dtype=np.float64).view(np.uint64)))
 
 
-def measure_plain_workload(w, steps, warmup):
+def measure_plain_workload(w, steps, warmup, with_oracle=True):
     """One plain workload: eval_and_diff per step, event-timed, beside the
     oracle on all host cores for the same inputs; outputs compared bitwise."""
     import torch
@@ -192,20 +192,28 @@ def measure_plain_workload(w, steps, warmup):
     ms = _step_times(lambda: P.eval_and_diff(coeff, z, value, grad), steps, warmup)
     info = P.plan.info
     work = info["n_conv"] * flops.conv_flops(w.m, w.d) + info["n_add"] * flops.add_flops(w.m, w.d)
+    chain = info["chain_layers"] > 0
+    launches = (1 if info["fused_components"] else
+                (1 + info["n_layers"] - info["chain_layers"]) if chain else info["n_layers"])
+    out = {"workload": w.name, "m": w.m, "d": w.d, "n": w.n, "N": w.N, "n_conv": info["n_conv"],
+           "n_add": info["n_add"], "conv_launches": launches,
+           "fused_layers": bool(info["fused_components"]), "ms_per_step": ms, "flop_per_step": work,
+           **_rate(work, ms["median"])}
+    if chain:
+        out["chain_launch"] = {k: info[k] for k in ("chain_layers", "chain_count", "chain_waves", "chain_window",
+                                                    "chain_ring")}
+    if not with_oracle:
+        return out
     cores, model = _cpu_info()
     sec, (ov, og) = _oracle_timed(lambda: O.eval_workload(w, nthreads=cores))
-    out = {"workload": w.name, "m": w.m, "d": w.d, "n": w.n, "N": w.N, "n_conv": info["n_conv"],
-           "n_add": info["n_add"], "conv_launches": info["n_layers"] if not info["fused_components"] else 1,
-           "fused_layers": bool(info["fused_components"]), "ms_per_step": ms, "flop_per_step": work,
-           **_rate(work, ms["median"]),
-           "bitexact_vs_oracle": _bits_equal(value, ov) and _bits_equal(grad, og),
-           "cpu_oracle": {"seconds": round(sec, 5), **_rate(work, sec * 1e3), "cores": cores, "cpu_model": model,
-                          "sample": "the whole workload, median of 3 runs"}}
+    out["bitexact_vs_oracle"] = _bits_equal(value, ov) and _bits_equal(grad, og)
+    out["cpu_oracle"] = {"seconds": round(sec, 5), **_rate(work, sec * 1e3), "cores": cores, "cpu_model": model,
+                         "sample": "the whole workload, median of 3 runs"}
     out["gpu_vs_cpu"] = round(sec * 1e3 / ms["median"], 1)
     return out
 
 
-def measure_autograd_workload(steps, warmup):
+def measure_autograd_workload(steps, warmup, with_oracle=True):
     """The differentiation workload: octo-double p1 at d = 32 through
     torch.autograd.Function (forward keeping the monomial products, backward
     the adjoint kernel), beside the oracle's value, gradient and adjoints."""
@@ -239,17 +247,20 @@ def measure_autograd_workload(steps, warmup):
     info = P.plan.info
     fwd_work = info["n_conv"] * flops.conv_flops(w.m, w.d) + info["n_add"] * flops.add_flops(w.m, w.d)
     rev_work = info["n_reverse"] * flops.conv_flops(w.m, w.d)
-    cores, model = _cpu_info()
 
     def oracle():
         ov, og = O.eval_workload(w, nthreads=cores)
         oc, oz = O.eval_adjoint(w.m, w.d, w.n, w.nvars, w.vars, w.z, og, ybar_np, nthreads=cores)
         return ov, og, oc, oz
 
+    work = fwd_work + rev_work
+    if not with_oracle:
+        return {"workload": w.name + "_autograd", "forward_ms": fwd, "reverse_ms": rev, "autograd_step_ms": ag,
+                **_rate(work, ag["median"]), "flop_per_step": work}
+    cores, model = _cpu_info()
     sec, (ov, og, oc, oz) = _oracle_timed(oracle)
     exact = (_bits_equal(value, ov) and _bits_equal(grad, og) and _bits_equal(cr.grad, oc) and
              _bits_equal(zr.grad, oz))
-    work = fwd_work + rev_work
     return {"workload": w.name + "_autograd", "m": w.m, "d": w.d, "n": w.n, "N": w.N,
             "forward_conv_jobs": info["n_conv"], "reverse_jobs": info["n_reverse"],
             "forward_ms": fwd, **{"forward_" + k: v for k, v in _rate(fwd_work, fwd["median"]).items()},
@@ -559,6 +570,25 @@ def run_sweep(a):
     print(json.dumps({"sweep": rows}), flush=True)
 
 
+def run_single(a):
+    """One of the other workloads on its own (for profiling): double double at
+    d = 8 (rand3), quad double p2 at d = 64, or the octo-double autograd pass;
+    the oracle beside it unless --no-cpu-baseline."""
+    from paper_2101_10881_amd import workloads as W
+    if a.workload == "autograd":
+        r = measure_autograd_workload(a.steps, a.warmup, not a.no_cpu_baseline)
+        ms = r["autograd_step_ms"]["median"]
+    else:
+        w = W.rand3() if a.workload == "rand3" else W.p2()
+        r = measure_plain_workload(w, a.steps, a.warmup, not a.no_cpu_baseline)
+        ms = r["ms_per_step"]["median"]
+    out = {"metric": "FP64 GFLOP/s (multi-double ops) for eval+gradient; % FP64 peak; batched vs plain",
+           "value": r["GFLOPs"], "unit": "GFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded random series)", "config": {"workload": r["workload"]}, "result": r}
+    print(json.dumps(out), flush=True)
+
+
 def load_tiles():
     """Autotuned tiles for the batched executor, if a cache for this device exists."""
     path = os.path.join(ROOT, "paper_2101_10881_amd", "tune_cache.json")
@@ -580,6 +610,8 @@ def main():
         return run_batch(a)
     if a.workload == "sweep":
         return run_sweep(a)
+    if a.workload in ("rand3", "p2", "autograd"):
+        return run_single(a)
     import torch
 
     from paper_2101_10881_amd import flops, mdpe

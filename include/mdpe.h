@@ -55,7 +55,7 @@ typedef struct {
                                increasing inside each monomial (Section 4) */
     uint32_t flags;         /* 0, or MDPE_KEEP_MONOMIAL_VALUES, MDPE_COMPLEX, MDPE_STREAM_OPERANDS,
                                MDPE_STAGE_OPERANDS, MDPE_ASAP_LAYERS, MDPE_FUSED_LAYERS,
-                               MDPE_LAYER_LAUNCHES, MDPE_CHAIN_LAUNCH */
+                               MDPE_LAYER_LAUNCHES, MDPE_CHAIN_LAUNCH, MDPE_NO_CHAIN_LAUNCH */
     const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
                                (every exponent one).  Monomial k is then
                                a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
@@ -138,7 +138,7 @@ typedef struct {
 
 /* Plan flag: run the chains of products in one pipelined launch (plans do so
  * by themselves where it is estimated well under the layered or fused
- * launches: chains of at least 8 products holding a quarter of the
+ * launches: chains of at least 16 products holding a quarter of the
  * convolutions or more, such as p2's).  A chain is a sequence of
  * convolutions where each job's first operand is the previous job's output
  * and its second a staged input series: the forward products f_j = f_{j-1} *
@@ -151,9 +151,13 @@ typedef struct {
  * sequential sum as in the per-layer launches, so every output bit is the
  * same.  Such plans give the in-place product b_{n-2} * a_k a fresh output
  * slot.  MDPE_EUNSUPPORTED when no chain qualifies or its first operands do
- * not fit in LDS; excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES and
- * MDPE_STREAM_OPERANDS. */
+ * not fit in LDS; excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES,
+ * MDPE_STREAM_OPERANDS and MDPE_NO_CHAIN_LAUNCH. */
 #define MDPE_CHAIN_LAUNCH 128u
+
+/* Plan flag: never the chain launch; the plan chooses between layered and
+ * fused launches as without it (excludes MDPE_CHAIN_LAUNCH). */
+#define MDPE_NO_CHAIN_LAUNCH 256u
 
 /* Plan summary. */
 typedef struct {
@@ -231,7 +235,7 @@ int plan_chain_jobs(const mdpe_plan *plan, int32_t *rows);
  * int32[64 * waves][*stride], row r for thread r of the chain's workgroup:
  * (j << 16) | k computes coefficient k of the j-th product (k+1 steps, its
  * terms i = 0..k in increasing i), (0x7FFF << 16) | (g-1) idles g steps, -1
- * ends the row.  *steps: steps every thread runs (a multiple of window).
+ * ends the row.  *steps: steps every thread runs (an even multiple of window).
  * codes NULL returns only *stride and *steps; else capacity is its length.
  */
 int chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t *codes,

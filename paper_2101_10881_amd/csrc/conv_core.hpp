@@ -316,6 +316,16 @@ __global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A,
     }
 }
 
+// A workgroup barrier that orders LDS accesses only: the LDS stores and
+// reads issued before it complete before any wavefront passes it, while
+// global loads in flight (second operands prefetched two steps ahead) and
+// global stores (read by later launches only) are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The chain launch.  Workgroup c runs chain c: products where each job's
 // first operand is the previous job's output and its second a staged input
 // series (the forward and backward products of Section 3).  Its lanes follow
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(256) void conv_fused_kernel(double *__restrict__ A,
 // coefficient by the job before it, beside its store to A.  Coefficient i of
 // a product is final after its own i+1 terms and the next product reads its
 // first operand in increasing i, so consecutive products overlap.  A
-// workgroup barrier after every S steps orders those LDS stores and reads: the
+// workgroup barrier on LDS after every S steps orders those stores and reads: the
 // host checks that the schedule reads each coefficient only in a window after
 // that of its store, and overwrites a slot only in a window after that of its
 // last read (check_chain_schedule).  Second operands stream from A two steps
@@ -425,7 +435,7 @@ __global__ __launch_bounds__(64 * WAVES) void conv_chain_kernel(double *__restri
         acc[l] = 0.0;
     }
     int until_barrier = S;
-    for (int s = 0; s < cc.steps; ++s) {
+    auto step = [&]() {
         St n2;
         advance(nx, n2);
         double x1[W], y1[W];
@@ -454,9 +464,17 @@ __global__ __launch_bounds__(64 * WAVES) void conv_chain_kernel(double *__restri
 #pragma unroll
         for (int l = 0; l < W; ++l) p[l] = pn[l];
         if (--until_barrier == 0) {
-            __syncthreads();
+            lds_barrier();
             until_barrier = S;
         }
+    };
+    // Two steps per iteration up to four doubles per coefficient, as in
+    // conv_group (the pipeline's copies become renames); the planner makes
+    // every chain's step count even.
+    constexpr int kU = W <= 4 ? 2 : 1;
+    for (int s = 0; s < cc.steps; s += kU) {
+        step();
+        if constexpr (kU == 2) step();
     }
 }
 

@@ -576,7 +576,8 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     if (!desc || !out) return fail(MDPE_EINVAL, "desc and out are required");
     *out = nullptr;
     if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS |
-                                MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES | MDPE_CHAIN_LAUNCH))
+                                MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES | MDPE_CHAIN_LAUNCH |
+                                MDPE_NO_CHAIN_LAUNCH))
         return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());

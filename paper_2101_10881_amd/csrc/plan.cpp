@@ -567,8 +567,10 @@ int make_chain_schedule(int L, int d, int W, int S, int B, std::vector<int32_t> 
             last_read[l] = std::max(last_read[l], start + k - 1);
         }
     }
+    // a multiple of the window, and even (the kernel may run two steps per iteration)
+    const int q = S % 2 ? 2 * S : S;
     int steps = *std::max_element(lane_free.begin(), lane_free.end());
-    steps = (steps + S - 1) / S * S;
+    steps = (steps + q - 1) / q * q;
     size_t st = 1;
     for (auto &x : lists) st = std::max(st, x.size() + 1);
     *stride = (int)st;
@@ -727,7 +729,10 @@ static double make_chain_plan(Plan &P, const std::vector<std::vector<int64_t>> &
     // a chain's workgroup holds a CU: W/4 wavefronts per SIMD, ceil(chains / CUs) rounds
     const long cus = kSimds / 4;
     const double rounds = std::ceil((double)chains.size() / cus);
-    const double chain_cost = rounds * worst * std::max(1.0, W / 4.0) * (1.0 + 0.02 * 4.0 / S);
+    // a chain step at one double per coefficient costs about 0.55 of a
+    // schedule step (measured on p2 at d = 8..152 against the dealt plans)
+    const double step = P.w == 1 ? 0.55 : 1.0;
+    const double chain_cost = rounds * worst * std::max(1.0, W / 4.0) * (1.0 + 0.02 * 4.0 / S) * step;
     return chain_cost + layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0, Lmax + 1);
 }
 
@@ -742,9 +747,13 @@ static int chain_ring_slots(const Plan &P, int Lmax) {
 
 // The chain launch for a plan without in-place jobs: the cheapest of W = 4,
 // 8 wavefronts and barriers every S = 1, 2, 4 steps, applied when forced or
-// estimated under 0.6 of `other` (the cost of the plan without it).  Returns
-// whether P now holds a chain launch.
-static constexpr bool kChainByDefault = false;
+// estimated under 0.9 of `other` (the cost of the plan without it).  On p2
+// (64 products per chain) that is every precision from two doubles on at
+// d = 8..152 (measured 1.3-7.4x faster) and one double at d = 31 and 64
+// (1.2-1.6x); one double at d >= 95 keeps its dealt per-layer plan (the
+// chain launch measured 1.3-1.9x slower there).  Returns whether P now holds
+// a chain launch.
+static constexpr bool kChainByDefault = true;
 
 static bool choose_chain_launch(Plan &P, bool forced, double other) {
     if (P.streamed) return false;
@@ -756,7 +765,7 @@ static bool choose_chain_launch(Plan &P, bool forced, double other) {
         Lmax = std::max(Lmax, (int)c.size());
         members += (long)c.size();
     }
-    if (!forced && (Lmax < 8 || 4 * members < (long)P.conv.size())) return false;
+    if (!forced && (Lmax < 16 || 4 * members < (long)P.conv.size())) return false;
     const int B = chain_ring_slots(P, Lmax);
     if (B < 2) return false;
     double best = -1;
@@ -771,7 +780,7 @@ static bool choose_chain_launch(Plan &P, bool forced, double other) {
                 bs = S;
             }
         }
-    if (best < 0 || (!forced && best >= 0.6 * other)) return false;
+    if (best < 0 || (!forced && best >= 0.9 * other)) return false;
     return make_chain_plan(P, chains, bw, bs, B) >= 0;
 }
 
@@ -787,9 +796,19 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     // the in-place products fresh output slots: a chain's products overlap,
     // so b_{n-2} must stay readable while b_{n-2} * a_k is stored.
     const bool chain_forced = (flags & kChainLaunch) != 0;
-    if (!P.streamed && !(flags & (kFusedLayers | kLayerLaunches)) && (chain_forced || (kChainByDefault && P.n_layers() >= 8))) {
-        double other = layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0);
-        if (fuse_by_default(P)) other = std::min(other, (double)P.n_layers() * make_lane_schedule(d, 1).steps);
+    if (!P.streamed && !(flags & (kFusedLayers | kLayerLaunches | kNoChainLaunch)) &&
+        (chain_forced || (kChainByDefault && P.n_layers() >= 16))) {
+        // the plan without it, in the layer cost model's units: dealt steps
+        // weigh what choose_staged_lanes gives them
+        const int Q = P.lanes.waves_per_job, J = P.lanes.jobs_per_group;
+        double other = P.simple ? layer_cost(P, Q, J, dealt_steps(d, J, Q), P.w == 1 ? 0.15 : 0.4)
+                                : layer_cost(P, Q, J, P.lanes.steps, 1.0);
+        if (fuse_by_default(P)) {
+            const LaneSchedule one = make_lane_schedule(d, 1);
+            const double per = prefer_simple_dealing(d, 1, P.w, one.steps) ? dealt_steps(d, 1) * (P.w == 1 ? 0.15 : 0.5)
+                                                                           : (double)one.steps;
+            other = std::min(other, P.n_layers() * per);
+        }
         Plan C;
         bool uns = false;
         std::string e2 = build_plan_mode(n, N, d, m, nvars, vars, exps, flags, false, true, C, &uns);
@@ -828,10 +847,11 @@ static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nv
                                    bool *unsupported) {
     *unsupported = false;
     if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers | kFusedLayers |
-                  kLayerLaunches | kChainLaunch))
+                  kLayerLaunches | kChainLaunch | kNoChainLaunch))
         return "unknown flags";
-    if ((flags & kChainLaunch) && (flags & (kFusedLayers | kLayerLaunches | kStreamOperands)))
-        return "MDPE_CHAIN_LAUNCH excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES and MDPE_STREAM_OPERANDS";
+    if ((flags & kChainLaunch) && (flags & (kFusedLayers | kLayerLaunches | kStreamOperands | kNoChainLaunch)))
+        return "MDPE_CHAIN_LAUNCH excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES, MDPE_STREAM_OPERANDS and "
+               "MDPE_NO_CHAIN_LAUNCH";
     if ((flags & kFusedLayers) && (flags & kLayerLaunches)) return "MDPE_FUSED_LAYERS and MDPE_LAYER_LAUNCHES exclude each other";
     if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;

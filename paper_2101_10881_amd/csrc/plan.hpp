@@ -43,6 +43,7 @@ constexpr uint32_t kAsapLayers = 16u;      // every convolution at its earliest 
 constexpr uint32_t kFusedLayers = 32u;     // all convolution layers in one launch, per independent component
 constexpr uint32_t kLayerLaunches = 64u;   // one launch per convolution layer (no automatic fusing)
 constexpr uint32_t kChainLaunch = 128u;    // first-operand chains in one pipelined launch (see Plan::pipe_*)
+constexpr uint32_t kNoChainLaunch = 256u;  // never the chain launch (the plan chooses the rest)
 
 // Chain launch: the code of an idle stretch in a lane's entry list (job field)
 constexpr int32_t kIdleJob = 0x7FFF;    // codes stay positive; chain jobs are numbered below it
@@ -159,7 +160,7 @@ std::string check_hazards(const Plan &P);
 // Chain launch schedule for one chain of L jobs of degree d on W wavefronts
 // with a workgroup barrier every S steps and first operands in B LDS slots:
 // codes (64W rows of *stride entries, the encoding of Plan::pipe_codes).
-// Returns the steps (a multiple of S).
+// Returns the steps (an even multiple of S).
 int make_chain_schedule(int L, int d, int W, int S, int B, std::vector<int32_t> &codes, int *stride);
 // Checks a chain schedule against the kernel's timing: every coefficient of
 // every job exactly once, within `steps`; the first operand of step t is read

@@ -28,6 +28,7 @@ MDPE_ASAP_LAYERS = 16
 MDPE_FUSED_LAYERS = 32
 MDPE_LAYER_LAUNCHES = 64
 MDPE_CHAIN_LAUNCH = 128
+MDPE_NO_CHAIN_LAUNCH = 256
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -95,6 +96,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    # torch first: its HIP runtime (torch/lib/libamdhip64.so, soname
+    # libamdhip64.so.7) then satisfies the library's dependency, so both share
+    # one runtime, one device context and one set of streams.  Loaded the
+    # other way round, torch's libraries ask for the unversioned file name,
+    # load a second runtime beside /opt/rocm's, and the library's HIP calls
+    # then found no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.plan_polynomial.argtypes = [ctypes.POINTER(PolyDesc), ctypes.c_int, ctypes.POINTER(_vp)]
     L.plan_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
@@ -369,8 +377,8 @@ class Polynomial:
     forces operands read from global memory (else staged in LDS) / every
     convolution layer in one launch (else one launch per layer).
     chain_launch: True forces the chains of products into one pipelined
-    launch (MDPE_CHAIN_LAUNCH); None lets the plan choose; fused_layers=False
-    excludes it too.
+    launch (MDPE_CHAIN_LAUNCH), False excludes it (MDPE_NO_CHAIN_LAUNCH), None
+    lets the plan choose; fused_layers=False excludes it too.
     asap_layers: every convolution at its earliest layer (no balancing).
     """
 
@@ -389,7 +397,8 @@ class Polynomial:
                  # fused_layers: None lets the plan choose, True / False forces it
                  (MDPE_FUSED_LAYERS if fused_layers is True else 0) |
                  (MDPE_LAYER_LAUNCHES if fused_layers is False else 0) |
-                 (MDPE_CHAIN_LAUNCH if chain_launch is True else 0))
+                 (MDPE_CHAIN_LAUNCH if chain_launch is True else 0) |
+                 (MDPE_NO_CHAIN_LAUNCH if chain_launch is False else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)

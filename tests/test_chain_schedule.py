@@ -100,7 +100,7 @@ def simulate(L, d, waves, window, ring, steps, codes):
 def test_schedules_pass_both_checks(L, d, waves, window):
     for ring in sorted({2, 3, max(2, min(L, 46)), max(2, L)}):
         codes, steps = mdpe.chain_schedule(L, d, waves, window, ring)
-        assert steps % window == 0
+        assert steps % window == 0 and steps % 2 == 0
         mdpe.check_chain_schedule(L, d, waves, window, ring, steps, codes)
         assert simulate(L, d, waves, window, ring, steps, codes) == ""
 

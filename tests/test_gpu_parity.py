@@ -133,6 +133,24 @@ def test_sweep_corners_bitexact(oracle_lib, poly, m, d):
     _compare(oracle_lib, build(m=m, d=d))
 
 
+@pytest.mark.parametrize("m,d", [(2, 31), (2, 152), (3, 152), (2, 66), (4, 64)])
+def test_p2_layered_plans_bitexact(oracle_lib, m, d):
+    # p2 runs its chains of products in the chain launch by default; its
+    # layered plan (two wavefronts per job at d >= 152, dealt coefficients at
+    # two doubles) stays available and must give the same bits
+    from paper_2101_10881_amd import mdpe
+    import torch
+    w = W.p2(m=m, d=d)
+    P = mdpe.Polynomial.for_workload(w, torch.device("cuda", 0), chain_launch=False)
+    assert P.plan.info["chain_layers"] == 0
+    _say(f"layered p2 m={m} d={d}: fused={P.plan.info['fused_components'] > 0} "
+         f"waves_per_job={P.plan.info['waves_per_job']}")
+    want_v, want_g = oracle_lib.eval_workload(w)
+    got_v, got_g = run_gpu(w, poly=P)
+    assert_bitexact(got_v, want_v, "value")
+    assert_bitexact(got_g, want_g, "gradient")
+
+
 @pytest.mark.parametrize("case", ["p1_m2", "p1_exponents_m2", "p1_m3_d32", "p1_keep_m1"])
 def test_balanced_layers_bitexact(oracle_lib, case):
     # p1's shape at these degrees plans with convolutions moved to later

@@ -63,7 +63,8 @@ def test_p1_counts():
 
 def test_p2_counts():
     g = json.load(open(os.path.join(GOLD, "paper_counts.json")))["p2"]
-    p = mdpe.Plan.for_workload(W.p2(), device=-1)
+    # the layered plan (the chain launch, chosen for p2 by default, relayers the cross products)
+    p = mdpe.Plan.for_workload(W.p2(), device=-1, flags=mdpe.MDPE_NO_CHAIN_LAUNCH)
     conv, add = p.layer_sizes()
     assert p.info["n_conv"] == g["n_conv"] and p.info["n_add"] == g["n_add"]
     assert conv[:31] == [g["first_31_conv_launches"]] * 31
@@ -249,7 +250,8 @@ def test_complex_plan_same_jobs_double_workspace():
 
 @pytest.mark.parametrize("flags, m, d, code", [
     (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
-    (256, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
+    (512, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
+    (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_NO_CHAIN_LAUNCH, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_FUSED_LAYERS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_STREAM_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_STREAM_OPERANDS | mdpe.MDPE_STAGE_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
@@ -380,7 +382,8 @@ def test_streaming_chosen_by_cost():
 def test_simple_dealing_choice(build, m, d, simple):
     # coefficients of at most two doubles are dealt to lanes in turn where the
     # planner estimates it faster than the lane schedule; never for more
-    assert mdpe.Plan.for_workload(build(m=m, d=d), device=-1).info["simple_dealing"] == simple
+    flags = mdpe.MDPE_NO_CHAIN_LAUNCH
+    assert mdpe.Plan.for_workload(build(m=m, d=d), device=-1, flags=flags).info["simple_dealing"] == simple
 
 
 @pytest.mark.parametrize("build,m,d,J,Q", [(W.p1, 10, 152, 1, 1), (W.p2, 4, 64, 2, 1),
@@ -391,7 +394,7 @@ def test_jobs_and_wavefronts_per_group(build, m, d, J, Q):
     # layers with fewer wavefronts than SIMDs (p2's 378 jobs) spread a job over
     # two wavefronts, down to the longest coefficient's d+1 steps; at one or two
     # doubles per coefficient by dealing the coefficients over them
-    i = mdpe.Plan.for_workload(build(m=m, d=d), device=-1).info
+    i = mdpe.Plan.for_workload(build(m=m, d=d), device=-1, flags=mdpe.MDPE_NO_CHAIN_LAUNCH).info
     assert (i["jobs_per_group"], i["waves_per_job"]) == (J, Q)
     if Q > 1:
         assert i["lane_steps"] == d + 1

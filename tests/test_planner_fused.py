@@ -100,7 +100,8 @@ def test_streamed_plans_do_not_fuse():
 
 
 def test_default_fuses_deep_plans_of_small_layers():
-    fused = lambda w, f=0: mdpe.Plan.for_workload(w, device=-1, flags=f).info["fused_components"] > 0
+    # among the layered and fused launches (p2 takes the chain launch by default)
+    fused = lambda w, f=mdpe.MDPE_NO_CHAIN_LAUNCH: mdpe.Plan.for_workload(w, device=-1, flags=f).info["fused_components"] > 0
     # p2: 64 layers of 378 jobs
     assert fused(W.p2(m=1, d=8)) and fused(W.p2()) and fused(W.p2(m=4, d=95)) and fused(W.p2(m=10, d=31))
     assert fused(W.p2(m=5, d=31)) and fused(W.p2(m=8, d=8))

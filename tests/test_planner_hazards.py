@@ -171,7 +171,7 @@ def test_multiwave_staged_plans_have_no_in_place_job(build, m, d):
     """A staged plan that spreads a job over several wavefronts gives the
     in-place multiplications fresh output slots (as streamed plans do)."""
     w = build(m=m, d=d)
-    p = mdpe.Plan.for_workload(w, device=-1)
+    p = mdpe.Plan.for_workload(w, device=-1, flags=mdpe.MDPE_NO_CHAIN_LAUNCH)
     assert p.info["waves_per_job"] > 1 and not p.info["streamed"]
     conv, add, out = _rows(p)
     assert not (conv[:, 1] == conv[:, 3]).any()
