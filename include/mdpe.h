@@ -317,6 +317,21 @@ int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, d
                   double *grad, void *workspace, void *stream);
 
 /*
+ * eval_and_diff without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a fixed array of
+ * 64 MiB (67108864 bytes) that the library holds on each device from load to
+ * process end; the call itself allocates nothing.  Plans whose
+ * plan_info().workspace_bytes exceed it are refused with MDPE_EUNSUPPORTED
+ * (use eval_and_diff).  Every call on one device shares that device's array:
+ * calls that overlap on one device (other streams, other threads) race, and
+ * the array keeps the last call's contents.  Arguments, launches and output
+ * bits are those of eval_and_diff.
+ */
+int eval_and_diff_noalloc(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
+                          double *grad, void *stream);
+
+/*
  * Reverse pass (needs MDPE_KEEP_MONOMIAL_VALUES).  For an upstream adjoint
  * ybar of the value series, L = sum_t ybar_t p_t, returns
  *   coeff_bar[k][s] = dL/da_k[s] = sum_{j=0..d-s} ybar[s+j] M_k[j]   (coeff_bar[0] = ybar)

@@ -31,6 +31,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -570,6 +571,40 @@ void launch_elementwise(int op, long count, const double *x, const double *y, do
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free entry --
+// eval_and_diff_noalloc runs on a workspace the library holds from load to
+// process end: one fixed array per device, sized for plans of up to
+// kScratchBytes of workspace (64 MiB: every series slot of p2 at quad double
+// and d = 64, 50.6 MB, or of p1 at octo double and d = 32 with the monomial
+// values kept).  Every call on a device shares that device's copy; calls that
+// overlap on one device race.  Nothing in it must start at zero: staging
+// writes the inputs, and every convolution and addition writes its output
+// slot before any job reads it.
+namespace {
+constexpr int64_t kScratchBytes = 64ll << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+// The array's device address on `device` (each device holds its own copy).
+// Looked up once per device, with that device current; host code uses this
+// address, never the array's name, wherever it needs the array's memory.
+int scratch_address(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices];
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        DeviceGuard g(device);
+        if (!g.ok) return fail(MDPE_EDEVICE, "cannot select the plan's device");
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MDPE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return MDPE_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
@@ -743,6 +778,23 @@ int plan_scale_jobs(const mdpe_plan *pl, int32_t *rows) {
 int eval_and_diff(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
                   void *workspace, void *stream) {
     return eval_impl(pl, coeff, z, value, grad, workspace, stream, nullptr);
+}
+
+int eval_and_diff_noalloc(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,
+                          void *stream) {
+    if (!pl) return fail(MDPE_EINVAL, "plan is NULL");
+    if (pl->device < 0 || pl->device >= kMaxDevices)
+        return fail(MDPE_EINVAL, "eval_and_diff_noalloc needs a device plan on devices 0..63");
+    const mdpe::Plan &P = pl->P;
+    const int64_t need = P.n_series * (int64_t)(P.d + 1) * P.w * (int64_t)sizeof(double);
+    if (need > kScratchBytes)
+        return fail(MDPE_EUNSUPPORTED, "eval_and_diff_noalloc: the plan needs a workspace of " + std::to_string(need) +
+                                           " bytes, above the library's fixed " + std::to_string(kScratchBytes) +
+                                           "; use eval_and_diff with a workspace of the caller");
+    void *ws = nullptr;
+    int rc = scratch_address(pl->device, &ws);
+    if (rc) return rc;
+    return eval_impl(pl, coeff, z, value, grad, ws, stream, nullptr);
 }
 
 int eval_and_diff_profiled(const mdpe_plan *pl, const double *coeff, const double *z, double *value, double *grad,

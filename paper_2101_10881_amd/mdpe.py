@@ -116,6 +116,7 @@ def lib():
     L.plan_outputs.argtypes = [_vp, _i32p]
     L.plan_scale_jobs.argtypes = [_vp, _i32p]
     L.eval_and_diff.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.eval_and_diff_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.eval_and_diff_profiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.profiler_create.argtypes = [ctypes.POINTER(_vp)]
     L.profiler_read.argtypes = [_vp, ctypes.POINTER(Times)]
@@ -306,6 +307,12 @@ def eval_and_diff(plan: Plan, coeff, z, value, grad, workspace, stream=None):
     """Enqueue one evaluation on `stream` (tensors on the plan's device)."""
     _check(lib().eval_and_diff(plan.handle, _ptr(coeff), _ptr(z), _ptr(value), _ptr(grad), _ptr(workspace),
                                _stream(stream)))
+
+
+def eval_and_diff_noalloc(plan: Plan, coeff, z, value, grad, stream=None):
+    """Enqueue one evaluation on `stream` over the library's fixed workspace."""
+    _check(lib().eval_and_diff_noalloc(plan.handle, _ptr(coeff), _ptr(z), _ptr(value), _ptr(grad),
+                                       _stream(stream)))
 
 
 MDPE_TIME_STAGE, MDPE_TIME_CONV, MDPE_TIME_ADD, MDPE_TIME_GATHER = 1, 2, 4, 8
