@@ -378,6 +378,8 @@ def batch_cpu_baseline(r, every=8):
 
 
 def run_batch(a):
+    if a.copy_calibration_mib:
+        copy_calibration(a.copy_calibration_mib)
     r = measure_batch(a.instances, a.steps, a.warmup)
     r.pop("_outputs")
     out = {
@@ -570,11 +572,25 @@ def run_sweep(a):
     print(json.dumps({"sweep": rows}), flush=True)
 
 
+def copy_calibration(mib):
+    """One plain device copy of `mib` MiB, so that a counter profile of the run
+    shows what FETCH_SIZE / WRITE_SIZE read for a known number of bytes."""
+    import torch
+    nbytes = mib << 20
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_single(a):
     """One of the other workloads on its own (for profiling): double double at
     d = 8 (rand3), quad double p2 at d = 64, or the octo-double autograd pass;
     the oracle beside it unless --no-cpu-baseline."""
     from paper_2101_10881_amd import workloads as W
+    if a.copy_calibration_mib:
+        copy_calibration(a.copy_calibration_mib)
     if a.workload == "autograd":
         r = measure_autograd_workload(a.steps, a.warmup, not a.no_cpu_baseline)
         ms = r["autograd_step_ms"]["median"]
@@ -629,12 +645,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     if a.copy_calibration_mib:
-        nbytes = a.copy_calibration_mib << 20
-        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(a.copy_calibration_mib)
 
     for _ in range(a.warmup):
         P.eval_and_diff(coeff, z, value, grad)

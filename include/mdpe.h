@@ -55,7 +55,8 @@ typedef struct {
                                increasing inside each monomial (Section 4) */
     uint32_t flags;         /* 0, or MDPE_KEEP_MONOMIAL_VALUES, MDPE_COMPLEX, MDPE_STREAM_OPERANDS,
                                MDPE_STAGE_OPERANDS, MDPE_ASAP_LAYERS, MDPE_FUSED_LAYERS,
-                               MDPE_LAYER_LAUNCHES, MDPE_CHAIN_LAUNCH, MDPE_NO_CHAIN_LAUNCH */
+                               MDPE_LAYER_LAUNCHES, MDPE_CHAIN_LAUNCH, MDPE_NO_CHAIN_LAUNCH,
+                               MDPE_SINGLE_LAUNCH */
     const int32_t *exps;    /* host [sum n_k] exponents in 1..64 aligned with vars, or NULL
                                (every exponent one).  Monomial k is then
                                a_k prod_j z_{i_j}^{e_j}: Section 3 writes it as the
@@ -159,6 +160,18 @@ typedef struct {
  * fused launches as without it (excludes MDPE_CHAIN_LAUNCH). */
 #define MDPE_NO_CHAIN_LAUNCH 256u
 
+/* Plan flag: the whole evaluation in one launch of one workgroup (plans do so
+ * by themselves where it is estimated under 0.7 of the per-launch time: plans
+ * so small that the boundaries between their ~10 dependent launches, ~4.5 us
+ * each on MI355X, dominate, such as 16 three-variable monomials at d = 8).
+ * The workgroup's wavefronts run staging, every convolution layer (each
+ * wavefront a group of jobs per round, as in a per-layer launch), the scale
+ * stage, every addition level and the gather, with a workgroup barrier after
+ * each.  Every output bit is that of the per-launch path.  Excludes
+ * MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES, MDPE_STREAM_OPERANDS and
+ * MDPE_CHAIN_LAUNCH. */
+#define MDPE_SINGLE_LAUNCH 512u
+
 /* Plan summary. */
 typedef struct {
     int64_t n_series;       /* series slots in the data array A: e/(d+1) of eq. (6) */
@@ -187,9 +200,11 @@ typedef struct {
     int32_t chain_layers;   /* MDPE_CHAIN_LAUNCH: layers 1..chain_layers run in the chain launch
                                (layer L: the L-th product of every chain); 0 without it */
     int32_t chain_count;    /* MDPE_CHAIN_LAUNCH: chains, one workgroup each */
-    int32_t chain_waves;    /* MDPE_CHAIN_LAUNCH: wavefronts per chain workgroup (4 or 8) */
+    int32_t chain_waves;    /* MDPE_CHAIN_LAUNCH: wavefronts per chain workgroup (4, 8, 12 or 16) */
     int32_t chain_window;   /* MDPE_CHAIN_LAUNCH: steps between workgroup barriers */
     int32_t chain_ring;     /* MDPE_CHAIN_LAUNCH: LDS slots of first operands per chain */
+    int32_t single_launch;  /* 1 if the whole evaluation runs in one workgroup (MDPE_SINGLE_LAUNCH) */
+    int32_t single_waves;   /* MDPE_SINGLE_LAUNCH: wavefronts of that workgroup */
 } mdpe_plan_info;
 
 /*
@@ -230,7 +245,7 @@ int plan_chain_jobs(const mdpe_plan *plan, int32_t *rows);
 
 /*
  * The lane schedule of one chain (host only): L products of degree d on
- * `waves` wavefronts (4 or 8), a workgroup barrier every `window` steps, the
+ * `waves` wavefronts (4, 8, 12 or 16), a workgroup barrier every `window` steps, the
  * first operands in `ring` LDS slots (job j's in slot j mod ring).  codes:
  * int32[64 * waves][*stride], row r for thread r of the chain's workgroup:
  * (j << 16) | k computes coefficient k of the j-th product (k+1 steps, its

@@ -35,21 +35,6 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
     st.i = 0;
 }
 
-// A job's three series as offsets (in doubles) into A: first operand, second
-// operand, output.  Kept in LDS, so that a lane starting a chain finds its
-// operands' addresses with one LDS read and an add.
-struct JobOffsets {
-    long x, y, z, unused;
-};
-
-// LDS layout of one wavefront's group: X[J][d+1][W] doubles (the first
-// operands), Y[J][d+1][W] (the second operands, only when
-// stages_second_operand(W)), then the J JobOffsets (16-byte aligned).
-// `doubles_per_coef` is lds_doubles_per_coef(W), or 0 for streamed operands.
-__host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
-__host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, int J) {
-    return conv_lds_jobs_offset((long)J * d1 * doubles_per_coef) + (long)J * (long)sizeof(JobOffsets);
-}
 
 // CORR = false: convolution z_k = sum_{i=0..k} x_i y_{k-i} (eq. (1)).
 // CORR = true:  correlation z_s = sum_{j=0..d-s} x_{s+j} y_j (the reverse pass);

@@ -59,16 +59,9 @@ __global__ __launch_bounds__(256) void add_level_kernel(double *__restrict__ A, 
 // A[dst] := e * A[src] at every coefficient of every scale job: one md_mul by
 // (e, 0, ..., 0) per part (general exponents, Section 3).
 template <int M, bool CX>
-__global__ __launch_bounds__(256) void scale_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
-                                                    long total, int d) {
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= total) return;
+__device__ __forceinline__ void scale_item(double *__restrict__ A, int4 t, int c, int d) {
     constexpr int W = kCoef<M, CX>;
-    const int d1 = d + 1;
-    const long q = idx / d1;
-    const int c = (int)(idx - q * d1);
-    const int4 t = jobs[q];
-    const long S = (long)d1 * W;
+    const long S = (long)(d + 1) * W;
     const double *in = A + (long)t.x * S + (long)c * W;
     double *out = A + (long)t.y * S + (long)c * W;
     double E[M], x[M], r[M];
@@ -82,6 +75,16 @@ __global__ __launch_bounds__(256) void scale_kernel(double *__restrict__ A, cons
 #pragma unroll
         for (int l = 0; l < M; ++l) out[part * M + l] = r[l];
     }
+}
+
+template <int M, bool CX>
+__global__ __launch_bounds__(256) void scale_kernel(double *__restrict__ A, const int4 *__restrict__ jobs,
+                                                    long total, int d) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int d1 = d + 1;
+    const long q = idx / d1;
+    scale_item<M, CX>(A, jobs[q], (int)(idx - q * d1), d);
 }
 
 __global__ __launch_bounds__(256) void stage_kernel(double *__restrict__ A, const double *__restrict__ coeff,
@@ -104,6 +107,80 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
     const int o = (int)(idx / d1);
     const int c = (int)(idx - (long)o * d1);
     gather_item(A, value, grad, out_slots[o], o, c, n, d, m);
+}
+
+// The whole evaluation in one launch of one workgroup, for plans so small
+// that the boundaries between dependent launches (~4.5 us each) would
+// dominate: staging, every convolution layer, the scale stage, every addition
+// level and the gather, each a phase of the workgroup's threads with a
+// workgroup barrier after it.  Each wavefront takes J convolution jobs per
+// round in its own LDS region of group_bytes, exactly as a per-layer launch's
+// group, so every output bit is that of the per-launch path.  The barrier
+// orders a phase's global stores before the next phase's loads within the
+// workgroup (one CU; workgroup-scope release and acquire), as between the
+// layers of the fused launch; A is read with vector loads only.
+struct SingleArgs {
+    double *A;
+    const double *coeff, *z;
+    double *value, *grad;
+    const int2 *stage;
+    int nstage;
+    const int4 *conv;
+    const int *conv_off;
+    int nl;
+    const int *chains;
+    int stride, steps, J, simple, group_bytes;
+    const int4 *scale;
+    int nscale;
+    const int2 *add;
+    const int *add_off;
+    int nlev;
+    const int *out;
+    int n, N, d;
+};
+
+template <int M, bool CX>
+__global__ __launch_bounds__(1024) void eval_single_kernel(SingleArgs a) {
+    constexpr int W = kCoef<M, CX>;
+    extern __shared__ double lds[];
+    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, waves = nt >> 6;
+    const int d1 = a.d + 1;
+    for (long it = tid; it < (long)a.nstage * d1; it += nt) {
+        const long e = it / d1;
+        stage_item(a.A, a.coeff, a.z, a.stage[e], (int)(it - e * d1), a.N, a.n, a.d, W);
+    }
+    __syncthreads();
+    double *mine = (double *)((char *)lds + (long)wave * a.group_bytes);
+    for (int L = 0; L < a.nl; ++L) {
+        const int lo = a.conv_off[L], hi = a.conv_off[L + 1];
+        // every wavefront runs the same rounds (conv_group ends its staging
+        // with a workgroup barrier, also for a wavefront without a job)
+        for (int r = lo; r < hi; r += waves * a.J) {
+            const int q = r + wave * a.J;
+            const int jn = q < hi ? min(a.J, hi - q) : 0;
+            conv_group<M, false, CX, false, false>(a.A, a.conv + (jn > 0 ? q : lo), jn, a.J, a.d, mine, a.chains,
+                                                   a.stride, a.steps, lane, lane, a.simple != 0);
+        }
+        __syncthreads();
+    }
+    for (long it = tid; it < (long)a.nscale * d1; it += nt) {
+        const long q = it / d1;
+        scale_item<M, CX>(a.A, a.scale[q], (int)(it - q * d1), a.d);
+    }
+    __syncthreads();
+    for (int r = 0; r < a.nlev; ++r) {
+        const long hi = (long)a.add_off[r + 1] * d1;
+        for (long it = (long)a.add_off[r] * d1 + tid; it < hi; it += nt) {
+            const long p = it / d1;
+            add_item<M, CX>(a.A, a.add[p], (int)(it - p * d1), a.d);
+        }
+        __syncthreads();
+    }
+    for (long it = tid; it < (long)(1 + a.n) * d1; it += nt) {
+        const int o = (int)(it / d1);
+        gather_item(a.A, a.value, a.grad, a.out[o], o, (int)(it - (long)o * d1), a.n, a.d, W);
+    }
 }
 
 // planar [m][count][d+1] series src[e] -> slot dst[e] (skipped when -1), for e < count
@@ -228,6 +305,9 @@ void free_plan(mdpe_plan *p) {
         (void)hipFree(p->d_pjobs);
         (void)hipFree(p->d_pcomps);
         (void)hipFree(p->d_pcodes);
+        (void)hipFree(p->d_coff);
+        (void)hipFree(p->d_aoff);
+        (void)hipFree(p->d_schains);
     }
     delete p;
 }
@@ -387,6 +467,10 @@ int launch_chain(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_chain_kernel<M, CX, 8>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_chain_kernel<M, CX, 12>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::conv_chain_kernel<M, CX, 16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
         attr_set[dv].store(true);
     }
     const unsigned chains = (unsigned)P.pipe_comps.size();
@@ -398,8 +482,14 @@ int launch_chain(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *
     else if (P.pipe_waves == 8)
         hipLaunchKernelGGL((mdpe::conv_chain_kernel<M, CX, 8>), dim3(chains), dim3(512), lds, st, A, pl->d_pjobs,
                            pl->d_pcomps, pl->d_pcodes, P.d, P.pipe_ring, P.pipe_window);
+    else if (P.pipe_waves == 12)
+        hipLaunchKernelGGL((mdpe::conv_chain_kernel<M, CX, 12>), dim3(chains), dim3(768), lds, st, A, pl->d_pjobs,
+                           pl->d_pcomps, pl->d_pcodes, P.d, P.pipe_ring, P.pipe_window);
+    else if (P.pipe_waves == 16)
+        hipLaunchKernelGGL((mdpe::conv_chain_kernel<M, CX, 16>), dim3(chains), dim3(1024), lds, st, A, pl->d_pjobs,
+                           pl->d_pcomps, pl->d_pcodes, P.d, P.pipe_ring, P.pipe_window);
     else
-        return fail(MDPE_EUNSUPPORTED, "chain launch: 4 or 8 wavefronts per chain");
+        return fail(MDPE_EUNSUPPORTED, "chain launch: 4, 8, 12 or 16 wavefronts per chain");
     LAUNCH_CHECK("conv_chain_kernel");
     return record(prof, 1, st, false);
 }
@@ -451,6 +541,62 @@ int launch_scale(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *
     return record(prof, 2, st, false);
 }
 
+// single launch: the whole evaluation in one workgroup of single_waves wavefronts
+template <int M, bool CX>
+int launch_single(const mdpe_plan *pl, double *A, const double *coeff, const double *z, double *value, double *grad,
+                  hipStream_t st, mdpe_profiler *prof) {
+    const mdpe::Plan &P = pl->P;
+    const int J = P.single_lanes.jobs_per_group;
+    const size_t gb = (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
+    const size_t lds = gb * (size_t)P.single_waves;
+    if (lds > (size_t)mdpe::kMaxLdsBytes) return fail(MDPE_EUNSUPPORTED, "single launch: LDS beyond one workgroup's");
+    static std::atomic<bool> attr_set[kMaxDevices];
+    const int dv = pl->device >= 0 && pl->device < kMaxDevices ? pl->device : 0;
+    if (!attr_set[dv].load()) {
+        HIP_TRY(hipFuncSetAttribute((const void *)mdpe::eval_single_kernel<M, CX>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mdpe::kMaxLdsBytes));
+        attr_set[dv].store(true);
+    }
+    mdpe::SingleArgs a;
+    a.A = A;
+    a.coeff = coeff;
+    a.z = z;
+    a.value = value;
+    a.grad = grad;
+    a.stage = pl->d_stage;
+    a.nstage = (int)P.stage.size();
+    a.conv = pl->d_conv;
+    a.conv_off = pl->d_coff;
+    a.nl = P.n_layers();
+    a.chains = pl->d_schains;
+    a.stride = P.single_lanes.stride;
+    a.steps = P.single_lanes.steps;
+    a.J = J;
+    a.simple = P.single_simple ? 1 : 0;
+    a.group_bytes = (int)gb;
+    a.scale = pl->d_scale;
+    a.nscale = (int)P.scale.size();
+    a.add = pl->d_add;
+    a.add_off = pl->d_aoff;
+    a.nlev = P.n_levels();
+    a.out = pl->d_out;
+    a.n = P.n;
+    a.N = P.N;
+    a.d = P.d;
+    int rc = record(prof, 1, st, true);
+    if (rc) return rc;
+    hipLaunchKernelGGL((mdpe::eval_single_kernel<M, CX>), dim3(1), dim3(64 * P.single_waves), lds, st, a);
+    LAUNCH_CHECK("eval_single_kernel");
+    return record(prof, 1, st, false);
+}
+
+template <int M>
+int run_single(const mdpe_plan *pl, double *A, const double *coeff, const double *z, double *value, double *grad,
+               hipStream_t st, mdpe_profiler *prof) {
+    return pl->P.complex_series() ? launch_single<M, true>(pl, A, coeff, z, value, grad, st, prof)
+                                  : launch_single<M, false>(pl, A, coeff, z, value, grad, st, prof);
+}
+
 template <int M, bool CX>
 int run_field(const mdpe_plan *pl, double *A, hipStream_t st, mdpe_profiler *prof) {
     int rc;
@@ -478,6 +624,18 @@ int eval_impl(const mdpe_plan *pl, const double *coeff, const double *z, double 
     double *A = (double *)workspace;
     const int d1 = P.d + 1;
     int rc;
+    if (P.single) {
+        switch (P.m) {
+            case 1: return run_single<1>(pl, A, coeff, z, value, grad, st, prof);
+            case 2: return run_single<2>(pl, A, coeff, z, value, grad, st, prof);
+            case 3: return run_single<3>(pl, A, coeff, z, value, grad, st, prof);
+            case 4: return run_single<4>(pl, A, coeff, z, value, grad, st, prof);
+            case 5: return run_single<5>(pl, A, coeff, z, value, grad, st, prof);
+            case 8: return run_single<8>(pl, A, coeff, z, value, grad, st, prof);
+            case 10: return run_single<10>(pl, A, coeff, z, value, grad, st, prof);
+            default: return fail(MDPE_EUNSUPPORTED, "unsupported m");
+        }
+    }
     {
         const long total = (long)P.stage.size() * d1;
         if ((rc = record(prof, 0, st, true))) return rc;
@@ -612,7 +770,7 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
     *out = nullptr;
     if (desc->flags & ~(uint32_t)(MDPE_KEEP_MONOMIAL_VALUES | MDPE_COMPLEX | MDPE_STREAM_OPERANDS | MDPE_STAGE_OPERANDS |
                                 MDPE_ASAP_LAYERS | MDPE_FUSED_LAYERS | MDPE_LAYER_LAUNCHES | MDPE_CHAIN_LAUNCH |
-                                MDPE_NO_CHAIN_LAUNCH))
+                                MDPE_NO_CHAIN_LAUNCH | MDPE_SINGLE_LAUNCH))
         return fail(MDPE_EINVAL, "unknown flags");
     if (device < -1) return fail(MDPE_EINVAL, "device must be >= -1");
     std::unique_ptr<mdpe_plan> pl(new (std::nothrow) mdpe_plan());
@@ -646,6 +804,7 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
         std::vector<int4> pjobs(P.pipe_jobs.size());
         for (size_t q = 0; q < P.pipe_jobs.size(); ++q)
             pjobs[q] = make_int4(P.pipe_jobs[q][0], P.pipe_jobs[q][1], P.pipe_jobs[q][2], 0);
+        std::vector<int32_t> coff(P.conv_off.begin(), P.conv_off.end()), aoff(P.add_off.begin(), P.add_off.end());
         std::vector<int2> add(P.add.size()), stage(P.stage.size());
         for (size_t q = 0; q < P.add.size(); ++q) add[q] = make_int2(P.add[q][0], P.add[q][1]);
         for (size_t q = 0; q < P.stage.size(); ++q) stage[q] = make_int2(P.stage[q][0], P.stage[q][1]);
@@ -666,7 +825,10 @@ int plan_polynomial(const mdpe_poly_desc *desc, int device, mdpe_plan **out) {
             (rc = upload(&raw->d_fchains, P.fused_lanes.chains.data(), P.fused_lanes.chains.size() * sizeof(int))) ||
             (rc = upload(&raw->d_pjobs, pjobs.data(), pjobs.size() * sizeof(int4))) ||
             (rc = upload(&raw->d_pcomps, P.pipe_comps.data(), P.pipe_comps.size() * sizeof(mdpe::ChainComp))) ||
-            (rc = upload(&raw->d_pcodes, P.pipe_codes.data(), P.pipe_codes.size() * sizeof(int)))) {
+            (rc = upload(&raw->d_pcodes, P.pipe_codes.data(), P.pipe_codes.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_coff, coff.data(), coff.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_aoff, aoff.data(), aoff.size() * sizeof(int))) ||
+            (rc = upload(&raw->d_schains, P.single_lanes.chains.data(), P.single_lanes.chains.size() * sizeof(int)))) {
             std::string keep = g_err;
             free_plan(pl.release());
             g_err = keep;
@@ -701,6 +863,8 @@ int plan_info(const mdpe_plan *pl, mdpe_plan_info *o) {
     o->chain_waves = P.pipe_waves;
     o->chain_window = P.pipe_window;
     o->chain_ring = P.pipe_ring;
+    o->single_launch = P.single ? 1 : 0;
+    o->single_waves = P.single_waves;
     o->flags = P.flags;
     o->n = P.n;
     o->N = P.N;
@@ -904,9 +1068,9 @@ int plan_chain_jobs(const mdpe_plan *pl, int32_t *rows) {
 
 int chain_schedule(int32_t L, int32_t d, int32_t waves, int32_t window, int32_t ring, int32_t *codes,
                    int64_t capacity, int32_t *stride, int32_t *steps) {
-    if (L < 1 || L > mdpe::kMaxChainLength || d < 0 || d > 4095 || (waves != 4 && waves != 8) || window < 1 ||
+    if (L < 1 || L > mdpe::kMaxChainLength || d < 0 || d > 4095 || waves < 4 || waves > 16 || waves % 4 || window < 1 ||
         ring < 2 || !stride || !steps || capacity < 0)
-        return fail(MDPE_EINVAL, "need 1 <= L <= 2048, 0 <= d <= 4095, waves 4 or 8, window >= 1, ring >= 2");
+        return fail(MDPE_EINVAL, "need 1 <= L <= 2048, 0 <= d <= 4095, waves 4, 8, 12 or 16, window >= 1, ring >= 2");
     std::vector<int32_t> cs;
     int st = 0;
     try {

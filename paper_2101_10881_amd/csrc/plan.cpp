@@ -726,13 +726,23 @@ static double make_chain_plan(Plan &P, const std::vector<std::vector<int64_t>> &
     P.pipe_codes.swap(codes);
     P.balanced = false;
     choose_staged_lanes(P, Lmax + 1);
-    // a chain's workgroup holds a CU: W/4 wavefronts per SIMD, ceil(chains / CUs) rounds
+    // a chain's workgroup holds a CU: k = W/4 wavefronts per SIMD, ceil(chains
+    // / CUs) rounds.  A lone wavefront keeps its SIMD's VALU about half busy
+    // (counters on c2: 0.49); k of them share it at eff(k) of k times the
+    // lone step's cost (measured on p2 at d = 31..152 and four, eight and ten
+    // doubles, the same schedules at 4..16 wavefronts: eff(2) = 0.80, eff(3)
+    // = 0.73, eff(4) = 0.70 up to five doubles per coefficient; 0.89, 0.81,
+    // 0.74 from eight on, where one step is long enough to fill the pipeline
+    // better).
     const long cus = kSimds / 4;
     const double rounds = std::ceil((double)chains.size() / cus);
+    const int k = std::max(1, W / 4);
+    static const double eff_short[5] = {1.0, 1.0, 0.80, 0.73, 0.70}, eff_long[5] = {1.0, 1.0, 0.89, 0.81, 0.74};
+    const double eff = P.w >= 8 ? eff_long[std::min(k, 4)] : eff_short[std::min(k, 4)];
     // a chain step at one double per coefficient costs about 0.55 of a
     // schedule step (measured on p2 at d = 8..152 against the dealt plans)
     const double step = P.w == 1 ? 0.55 : 1.0;
-    const double chain_cost = rounds * worst * std::max(1.0, W / 4.0) * (1.0 + 0.02 * 4.0 / S) * step;
+    const double chain_cost = rounds * worst * k * eff * (1.0 + 0.02 * 4.0 / S) * step;
     return chain_cost + layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0, Lmax + 1);
 }
 
@@ -746,7 +756,7 @@ static int chain_ring_slots(const Plan &P, int Lmax) {
 }
 
 // The chain launch for a plan without in-place jobs: the cheapest of W = 4,
-// 8 wavefronts and barriers every S = 1, 2, 4 steps, applied when forced or
+// 8, 12, 16 wavefronts and barriers every S = 1, 2, 4 steps, applied when forced or
 // estimated under 0.9 of `other` (the cost of the plan without it).  On p2
 // (64 products per chain) that is every precision from two doubles on at
 // d = 8..152 (measured 1.3-7.4x faster) and one double at d = 31 and 64
@@ -770,8 +780,11 @@ static bool choose_chain_launch(Plan &P, bool forced, double other) {
     if (B < 2) return false;
     double best = -1;
     int bw = 0, bs = 0;
-    for (int W : {4, 8})
+    // up to 16 wavefronts (1024 threads, at most 128 VGPRs each: not for ten
+    // doubles per coefficient, whose chain kernel needs 134)
+    for (int W : {4, 8, 12, 16})
         for (int S : {1, 2, 4}) {
+            if (W == 16 && P.w > 8) continue;
             Plan T = P;
             const double c = make_chain_plan(T, chains, W, S, B);
             if (c >= 0 && (best < 0 || c < best)) {
@@ -784,8 +797,108 @@ static bool choose_chain_launch(Plan &P, bool forced, double other) {
     return make_chain_plan(P, chains, bw, bs, B) >= 0;
 }
 
-std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
-                       uint32_t flags, Plan &P, bool *unsupported) {
+// ----------------------------------------------------------- single launch
+// FP64 instructions of one md_add / md_mul of the specification (two_sum = 6
+// additions, two_prod = 1 mul + 1 fma; the closed forms of the accounting).
+static long md_instr(bool mul, int m) {
+    const long rs = m >= 2 ? 2 * m - 3 : 0;
+    if (!mul) return 6 * ((long)m * (m - 1) / 2 + rs) + m;
+    long ntp = m >= 2 ? (m - 1) + (long)(m - 2) * (m - 1) / 2 : 0;
+    long tse = m >= 2 ? (long)(m - 2) * (m - 1) / 2 : 0;
+    long tsp = 0, plain = m - 1;
+    for (int k = 1; k < m - 1; ++k) {
+        tsp += (long)k * (2 * m - 3 - 2 * k);
+        plain += 2 * k;
+    }
+    return 6 * (tse + tsp + rs) + plain + (ntp + 1) + (ntp + 2 * (m - 1));
+}
+
+// Estimated microseconds of a plan's evaluation: per-launch (the kernel
+// boundary of ~4.5 us between dependent launches, measured on MI355X, plus
+// each launch's rounds of the SIMDs) against one workgroup of `waves`
+// wavefronts that runs every stage.  A multiply-add step of one wavefront
+// costs its md instructions plus ~50 of bookkeeping, 4 cycles each at
+// ~2.2 GHz; a wavefront sharing its SIMD with k-1 others takes k times as
+// long.  Dealt coefficients (w <= 2) take the measured weight of their steps.
+struct SingleCost {
+    double multi_us, single_us;
+    int waves;
+    LaneSchedule lanes;
+    bool simple;
+};
+
+static SingleCost single_launch_cost(const Plan &P) {
+    const bool cx = P.complex_series();
+    const long mul = cx ? 4 * md_instr(true, P.m) + 2 * md_instr(false, P.m) : md_instr(true, P.m);
+    const long add = (cx ? 2 : 1) * md_instr(false, P.m);
+    const double step_us = (double)(mul + add + 50) * 4 / 2200.0;
+    const double add_us = (double)(add + 20) * 4 / 2200.0;
+    const double boundary_us = 4.5;
+    const long d1 = P.d + 1;
+    SingleCost c{0, 0, 0, LaneSchedule(), false};
+    // per launch
+    const int J = P.lanes.jobs_per_group, Q = P.lanes.waves_per_job;
+    const double lsteps = P.simple ? dealt_steps(P.d, J, Q) * (P.w == 1 ? 0.15 : 0.4) : (double)P.lanes.steps;
+    long launches = 2 + P.n_layers() + P.n_levels() + (P.scale.empty() ? 0 : 1);
+    c.multi_us = launches * boundary_us;
+    for (int L = 1; L <= P.n_layers(); ++L) {
+        const long waves = (P.conv_off[L] - P.conv_off[L - 1] + J - 1) / J * Q;
+        c.multi_us += std::ceil(waves / (double)kSimds) * lsteps * step_us;
+    }
+    for (int r = 1; r <= P.n_levels(); ++r) {
+        const long items = (P.add_off[r] - P.add_off[r - 1]) * d1;
+        c.multi_us += std::ceil(items / (256.0 * kSimds)) * add_us;
+    }
+    // one workgroup: the cheapest of 4, 8 and 16 wavefronts, one-wavefront
+    // groups of J0 (or fewer) jobs within the LDS of the workgroup
+    c.single_us = -1;
+    const long stage_items = (long)P.stage.size() * d1, gather_items = (long)(1 + P.n) * d1;
+    for (int W : {4, 8, 16}) {
+        const int lds_per_coef = lds_doubles_per_coef(P.w);
+        for (int Js = choose_jobs_per_group(P.d, P.w);; Js = std::max(1, Js / 2)) {
+            const long bytes = (group_lds_bytes(d1, lds_per_coef, Js) + 15) / 16 * 16;
+            if (bytes * W <= kMaxLdsBytes) {
+                const LaneSchedule ls = make_lane_schedule(P.d, Js);
+                const bool simple = prefer_simple_dealing(P.d, Js, P.w, ls.steps);
+                const double st = simple ? dealt_steps(P.d, Js) * (P.w == 1 ? 0.15 : 0.5) : (double)ls.steps;
+                const double share = W / 4.0;  // wavefronts per SIMD
+                double u = boundary_us;
+                for (int L = 1; L <= P.n_layers(); ++L) {
+                    const long jobs = P.conv_off[L] - P.conv_off[L - 1];
+                    u += std::ceil(jobs / (double)(W * Js)) * st * step_us * share + 0.5;
+                }
+                const double threads = 64.0 * W;
+                for (int r = 1; r <= P.n_levels(); ++r)
+                    u += std::ceil((P.add_off[r] - P.add_off[r - 1]) * d1 / threads) * add_us * share + 0.5;
+                u += std::ceil((double)P.scale.size() * d1 / threads) * step_us * share;
+                u += std::ceil((stage_items + gather_items) / threads) * 0.2 + 1.0;
+                if (c.single_us < 0 || u < c.single_us) {
+                    c.single_us = u;
+                    c.waves = W;
+                    c.lanes = ls;
+                    c.simple = simple;
+                }
+                break;
+            }
+            if (Js == 1) break;
+        }
+    }
+    return c;
+}
+
+static bool choose_single_launch(Plan &P, bool forced) {
+    if (P.streamed || P.pipe_layers > 0 || P.fused_components > 0) return false;
+    const SingleCost c = single_launch_cost(P);
+    if (c.single_us < 0 || (!forced && c.single_us >= 0.7 * c.multi_us)) return false;
+    P.single = true;
+    P.single_waves = c.waves;
+    P.single_lanes = c.lanes;
+    P.single_simple = c.simple;
+    return true;
+}
+
+static std::string build_plan_launches(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
+                                       const int32_t *exps, uint32_t flags, Plan &P, bool *unsupported) {
     // Staged operands unless asked otherwise, or unless they do not fit in
     // LDS, or unless streaming with several wavefronts per job is estimated
     // to be faster (large d with few jobs per layer).
@@ -827,7 +940,7 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
         if (P.streamed) return err;
         if (flags & kFusedLayers)
             fuse_layers(P);
-        else if (!(flags & kLayerLaunches) && fuse_by_default(P) && fuse_layers(P) > 4)
+        else if (!(flags & (kLayerLaunches | kSingleLaunch)) && fuse_by_default(P) && fuse_layers(P) > 4)
             unfuse(P);  // a component would need several rounds per layer
         return err;
     };
@@ -842,16 +955,37 @@ std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const i
     return fuse();
 }
 
+// The plan's launch structure (per layer, fused, chain launch or streamed),
+// then, for plans so small that kernel boundaries dominate, the single launch.
+std::string build_plan(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars, const int32_t *exps,
+                       uint32_t flags, Plan &P, bool *unsupported) {
+    const bool forced = (flags & kSingleLaunch) != 0;
+    std::string err = build_plan_launches(n, N, d, m, nvars, vars, exps, forced ? flags | kNoChainLaunch : flags, P,
+                                          unsupported);
+    if (!err.empty()) return err;
+    P.flags = flags;
+    if (forced || !(flags & (kLayerLaunches | kFusedLayers | kChainLaunch | kStreamOperands))) {
+        if (!choose_single_launch(P, forced) && forced) {
+            *unsupported = true;
+            return "MDPE_SINGLE_LAUNCH: a job group does not fit in the workgroup's LDS";
+        }
+    }
+    return "";
+}
+
 static std::string build_plan_mode(int n, int N, int d, int m, const int32_t *nvars, const int32_t *vars,
                                    const int32_t *exps, uint32_t flags, bool stream, bool no_inplace, Plan &P,
                                    bool *unsupported) {
     *unsupported = false;
     if (flags & ~(kKeepMonomialValues | kComplex | kStreamOperands | kStageOperands | kAsapLayers | kFusedLayers |
-                  kLayerLaunches | kChainLaunch | kNoChainLaunch))
+                  kLayerLaunches | kChainLaunch | kNoChainLaunch | kSingleLaunch))
         return "unknown flags";
     if ((flags & kChainLaunch) && (flags & (kFusedLayers | kLayerLaunches | kStreamOperands | kNoChainLaunch)))
         return "MDPE_CHAIN_LAUNCH excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES, MDPE_STREAM_OPERANDS and "
                "MDPE_NO_CHAIN_LAUNCH";
+    if ((flags & kSingleLaunch) && (flags & (kFusedLayers | kLayerLaunches | kStreamOperands | kChainLaunch)))
+        return "MDPE_SINGLE_LAUNCH excludes MDPE_FUSED_LAYERS, MDPE_LAYER_LAUNCHES, MDPE_STREAM_OPERANDS and "
+               "MDPE_CHAIN_LAUNCH";
     if ((flags & kFusedLayers) && (flags & kLayerLaunches)) return "MDPE_FUSED_LAYERS and MDPE_LAYER_LAUNCHES exclude each other";
     if ((flags & kStreamOperands) && (flags & kStageOperands)) return "MDPE_STREAM_OPERANDS and MDPE_STAGE_OPERANDS exclude each other";
     const bool keep = (flags & kKeepMonomialValues) != 0;

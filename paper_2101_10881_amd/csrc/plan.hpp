@@ -35,6 +35,22 @@ struct LaneSchedule {
 __host__ __device__ constexpr bool stages_second_operand(int w) { return w <= 2; }
 __host__ __device__ constexpr int lds_doubles_per_coef(int w) { return stages_second_operand(w) ? 2 * w : w; }
 
+// A job's three series as offsets (in doubles) into A: first operand, second
+// operand, output.  Kept in LDS, so that a lane starting a chain finds its
+// operands' addresses with one LDS read and an add.
+struct JobOffsets {
+    long x, y, z, unused;
+};
+
+// LDS layout of one wavefront's group: X[J][d+1][W] doubles (the first
+// operands), Y[J][d+1][W] (the second operands, only when
+// stages_second_operand(W)), then the J JobOffsets (16-byte aligned).
+// `doubles_per_coef` is lds_doubles_per_coef(W), or 0 for streamed operands.
+__host__ __device__ inline long conv_lds_jobs_offset(long xdoubles) { return (xdoubles * 8 + 15) / 16 * 16; }
+__host__ __device__ inline long group_lds_bytes(long d1, int doubles_per_coef, int J) {
+    return conv_lds_jobs_offset((long)J * d1 * doubles_per_coef) + (long)J * (long)sizeof(JobOffsets);
+}
+
 constexpr uint32_t kKeepMonomialValues = 1u;
 constexpr uint32_t kComplex = 2u;          // complex series: real limbs, then imaginary limbs
 constexpr uint32_t kStreamOperands = 4u;   // read both convolution operands from global memory
@@ -44,6 +60,7 @@ constexpr uint32_t kFusedLayers = 32u;     // all convolution layers in one laun
 constexpr uint32_t kLayerLaunches = 64u;   // one launch per convolution layer (no automatic fusing)
 constexpr uint32_t kChainLaunch = 128u;    // first-operand chains in one pipelined launch (see Plan::pipe_*)
 constexpr uint32_t kNoChainLaunch = 256u;  // never the chain launch (the plan chooses the rest)
+constexpr uint32_t kSingleLaunch = 512u;   // the whole evaluation in one launch of one workgroup
 
 // Chain launch: the code of an idle stretch in a lane's entry list (job field)
 constexpr int32_t kIdleJob = 0x7FFF;    // codes stay positive; chain jobs are numbered below it
@@ -126,6 +143,15 @@ struct Plan {
     std::vector<std::array<int32_t, 3>> pipe_jobs;
     std::vector<ChainComp> pipe_comps;
     std::vector<int32_t> pipe_codes;
+    // Single launch (kSingleLaunch, or chosen by the cost model for plans so
+    // small that kernel boundaries dominate): one workgroup of single_waves
+    // wavefronts runs staging, every convolution layer (single_lanes.jobs_per_group
+    // jobs per wavefront and round), the scale stage, every addition level
+    // and the gather, with a workgroup barrier after each.
+    bool single = false;
+    int single_waves = 0;
+    LaneSchedule single_lanes;
+    bool single_simple = false;
     int n_layers() const { return (int)conv_off.size() - 1; }
     int n_levels() const { return (int)add_off.size() - 1; }
 };

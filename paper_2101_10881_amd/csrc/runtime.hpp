@@ -32,6 +32,9 @@ struct mdpe_plan {
     int4 *d_pjobs = nullptr;   // chain launch: jobs chain after chain
     mdpe::ChainComp *d_pcomps = nullptr;  // chain launch: one per chain
     int *d_pcodes = nullptr;   // chain launch: lane schedules
+    int *d_coff = nullptr;     // single launch: convolution layer offsets (int32)
+    int *d_aoff = nullptr;     // single launch: addition level offsets (int32)
+    int *d_schains = nullptr;  // single launch: the lane schedule of its job groups
 };
 
 namespace mdpe {

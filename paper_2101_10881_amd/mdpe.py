@@ -29,6 +29,7 @@ MDPE_FUSED_LAYERS = 32
 MDPE_LAYER_LAUNCHES = 64
 MDPE_CHAIN_LAUNCH = 128
 MDPE_NO_CHAIN_LAUNCH = 256
+MDPE_SINGLE_LAUNCH = 512
 SUPPORTED_M = (1, 2, 3, 4, 5, 8, 10)
 
 
@@ -54,7 +55,8 @@ class PlanInfo(ctypes.Structure):
                 ("simple_dealing", ctypes.c_int32), ("balanced_layers", ctypes.c_int32),
                 ("fused_components", ctypes.c_int32), ("fused_waves", ctypes.c_int32),
                 ("chain_layers", ctypes.c_int32), ("chain_count", ctypes.c_int32), ("chain_waves", ctypes.c_int32),
-                ("chain_window", ctypes.c_int32), ("chain_ring", ctypes.c_int32)]
+                ("chain_window", ctypes.c_int32), ("chain_ring", ctypes.c_int32),
+                ("single_launch", ctypes.c_int32), ("single_waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -386,12 +388,14 @@ class Polynomial:
     chain_launch: True forces the chains of products into one pipelined
     launch (MDPE_CHAIN_LAUNCH), False excludes it (MDPE_NO_CHAIN_LAUNCH), None
     lets the plan choose; fused_layers=False excludes it too.
+    single_launch: True forces the whole evaluation into one workgroup's
+    launch (MDPE_SINGLE_LAUNCH; plans choose it by themselves when tiny).
     asap_layers: every convolution at its earliest layer (no balancing).
     """
 
     def __init__(self, n, nvars, vars_, d, m, device=None, keep_monomials=False, complex=False, exps=None,
                  stream_operands=None, asap_layers=False, fused_layers=None, alloc_workspace=True,
-                 chain_launch=None):
+                 chain_launch=None, single_launch=False):
         import torch
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
@@ -405,7 +409,8 @@ class Polynomial:
                  (MDPE_FUSED_LAYERS if fused_layers is True else 0) |
                  (MDPE_LAYER_LAUNCHES if fused_layers is False else 0) |
                  (MDPE_CHAIN_LAUNCH if chain_launch is True else 0) |
-                 (MDPE_NO_CHAIN_LAUNCH if chain_launch is False else 0))
+                 (MDPE_NO_CHAIN_LAUNCH if chain_launch is False else 0) |
+                 (MDPE_SINGLE_LAUNCH if single_launch else 0))
         self.plan = Plan(n, nvars, vars_, d, m, self.device.index or 0, flags, exps)
         self.n, self.N, self.d, self.m = int(n), int(self.plan.info["N"]), int(d), int(m)
         self.complex = bool(complex)
@@ -418,10 +423,10 @@ class Polynomial:
 
     @classmethod
     def for_workload(cls, w, device=None, keep_monomials=False, stream_operands=None, asap_layers=False,
-                     fused_layers=None, alloc_workspace=True, chain_launch=None):
+                     fused_layers=None, alloc_workspace=True, chain_launch=None, single_launch=False):
         return cls(w.n, w.nvars, w.vars, w.d, w.m, device, keep_monomials, getattr(w, "cx", False),
                    getattr(w, "exps", None), stream_operands, asap_layers, fused_layers, alloc_workspace,
-                   chain_launch)
+                   chain_launch, single_launch)
 
     def new_workspace(self):
         import torch

@@ -96,7 +96,7 @@ def simulate(L, d, waves, window, ring, steps, codes):
 
 @pytest.mark.parametrize("L, d", [(1, 0), (2, 0), (3, 1), (5, 8), (64, 64), (63, 64), (20, 130), (40, 31),
                                   (8, 200)])
-@pytest.mark.parametrize("waves, window", [(4, 1), (4, 2), (4, 4), (8, 1), (8, 3)])
+@pytest.mark.parametrize("waves, window", [(4, 1), (4, 2), (4, 4), (8, 1), (8, 3), (12, 2), (16, 1)])
 def test_schedules_pass_both_checks(L, d, waves, window):
     for ring in sorted({2, 3, max(2, min(L, 46)), max(2, L)}):
         codes, steps = mdpe.chain_schedule(L, d, waves, window, ring)
@@ -204,7 +204,7 @@ def test_schedule_arguments_are_checked():
     with pytest.raises(mdpe.MdpeError):
         mdpe.chain_schedule(0, 4, 4, 1, 2)
     with pytest.raises(mdpe.MdpeError):
-        mdpe.chain_schedule(4, 4, 5, 1, 2)      # 4 or 8 wavefronts
+        mdpe.chain_schedule(4, 4, 6, 1, 2)      # 4, 8, 12 or 16 wavefronts
     with pytest.raises(mdpe.MdpeError):
         mdpe.chain_schedule(4, 4, 4, 1, 1)      # at least two slots
 

@@ -250,7 +250,9 @@ def test_complex_plan_same_jobs_double_workspace():
 
 @pytest.mark.parametrize("flags, m, d, code", [
     (mdpe.MDPE_COMPLEX | mdpe.MDPE_KEEP_MONOMIAL_VALUES, 2, 3, mdpe.MDPE_EUNSUPPORTED),  # no complex reverse pass
-    (512, 2, 3, mdpe.MDPE_EINVAL),                           # unknown flag
+    (1024, 2, 3, mdpe.MDPE_EINVAL),                          # unknown flag
+    (mdpe.MDPE_SINGLE_LAUNCH | mdpe.MDPE_LAYER_LAUNCHES, 2, 3, mdpe.MDPE_EINVAL),
+    (mdpe.MDPE_SINGLE_LAUNCH | mdpe.MDPE_CHAIN_LAUNCH, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_NO_CHAIN_LAUNCH, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_FUSED_LAYERS, 2, 3, mdpe.MDPE_EINVAL),
     (mdpe.MDPE_CHAIN_LAUNCH | mdpe.MDPE_STREAM_OPERANDS, 2, 3, mdpe.MDPE_EINVAL),
@@ -398,3 +400,23 @@ def test_jobs_and_wavefronts_per_group(build, m, d, J, Q):
     assert (i["jobs_per_group"], i["waves_per_job"]) == (J, Q)
     if Q > 1:
         assert i["lane_steps"] == d + 1
+
+
+def test_single_launch_for_tiny_plans_only():
+    """Plans whose ~10 dependent launches would cost more than their work run
+    in one workgroup's launch: 16 monomials of 3 of 8 variables at d = 8 do,
+    p1, p2, p3 and the mixed batch's instances do not; the flag forces it,
+    and the per-layer flag excludes it."""
+    info = lambda w, f=0: mdpe.Plan.for_workload(w, device=-1, flags=f).info
+    i = info(W.rand3())
+    assert i["single_launch"] == 1 and i["single_waves"] in (4, 8, 16)
+    for w in (W.p1(m=2, d=8), W.p2(m=1, d=8), W.p3(m=1, d=8), W.p1()):
+        assert info(w)["single_launch"] == 0
+    assert all(info(w)["single_launch"] == 0 for w in W.mixed_batch(64, seed=1))
+    assert info(W.rand3(), mdpe.MDPE_LAYER_LAUNCHES)["single_launch"] == 0
+    forced = info(W.p1(m=2, d=8), mdpe.MDPE_SINGLE_LAUNCH)
+    assert forced["single_launch"] == 1 and forced["chain_layers"] == 0 and forced["fused_components"] == 0
+    # the jobs and layers are the plan's own: the single launch only changes how they are launched
+    a = mdpe.Plan.for_workload(W.rand3(), device=-1, flags=mdpe.MDPE_LAYER_LAUNCHES)
+    b = mdpe.Plan.for_workload(W.rand3(), device=-1)
+    assert np.array_equal(a.conv_jobs(), b.conv_jobs()) and np.array_equal(a.add_jobs(), b.add_jobs())
