@@ -435,6 +435,9 @@ typedef struct {
     int32_t jobs_per_group;     /* convolution jobs per wavefront pass (lane schedule) */
     int32_t groups_per_task;    /* passes per convolution task */
     int32_t add_items_per_task; /* coefficients per addition / staging / gather task */
+    int32_t deal;               /* coefficients of at most two doubles: 0 the cost model's choice,
+                                   1 the lane schedule, 2 dealt to the lanes in turn (either gives
+                                   the same bits); ignored from three doubles on */
 } mdpe_batch_tile;
 
 typedef struct {

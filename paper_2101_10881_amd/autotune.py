@@ -5,6 +5,8 @@ A tile, per (m, d) bucket, is
     jobs_per_group     convolution jobs per wavefront pass (lane schedule)
     groups_per_task    passes per convolution task
     add_items_per_task coefficients per addition / staging / gather task
+    deal               at two doubles: the cost model's choice (0), the lane
+                       schedule (1) or coefficients dealt to lanes in turn (2)
 
 The tiles of all buckets interact: the persistent kernel's LDS size, hence
 its occupancy, is the maximum over instances, and every bucket's tasks share
@@ -41,8 +43,9 @@ def default_jobs_per_group(d: int) -> int:
 def candidates(m: int, d: int):
     J0 = default_jobs_per_group(d)
     js = sorted({J0, max(1, J0 // 2), min(64, 2 * J0)})
-    for J, G, A in itertools.product(js, [1, 2, 4, 8, 16], [1024, 4096, 16384]):
-        yield {"m": m, "d": d, "jobs_per_group": J, "groups_per_task": G, "add_items_per_task": A}
+    deals = [0, 1, 2] if m <= 2 else [0]
+    for J, G, A, D in itertools.product(js, [1, 2, 4, 8, 16], [1024, 4096, 16384], deals):
+        yield {"m": m, "d": d, "jobs_per_group": J, "groups_per_task": G, "add_items_per_task": A, "deal": D}
 
 
 def main():

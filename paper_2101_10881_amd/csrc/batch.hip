@@ -86,16 +86,26 @@ __device__ void run_task(const BatchTask &T, const BatchInst &I, double *lds, in
             __syncthreads();
         }
     } else {
+        // item T.first + q, q = lane, lane + 64, ...: series e, coefficient c.
+        // One 64-bit division per lane and task; each iteration then adds
+        // (64 / d1, 64 % d1) with a carry.
+        const long f = T.first + lane;
+        long e = f / d1;
+        int c = (int)(f - e * d1);
+        const int qe = 64 / d1, qc = 64 - qe * d1;
         for (int q = lane; q < T.count; q += 64) {
-            const long it = T.first + q;
-            const long e = it / d1;
-            const int c = (int)(it - e * d1);
             if (kind == 0)
                 stage_item(I.A, I.coeff, I.z, I.stage[e], c, I.N, I.n, I.d, M);
             else if (kind == 2)
                 add_item<M>(I.A, I.add[e], c, I.d);
             else
                 gather_item(I.A, I.value, I.grad, I.out[e], (int)e, c, I.n, I.d, M);
+            e += qe;
+            c += qc;
+            if (c >= d1) {
+                c -= d1;
+                ++e;
+            }
         }
     }
 }
@@ -420,11 +430,12 @@ std::string read_tune_cache(const char *path, const std::string &arch, std::vect
             out = (int32_t)x->num;
             return true;
         };
-        mdpe_batch_tile tile{0, 0, 0, 0, 0};
+        mdpe_batch_tile tile{0, 0, 0, 0, 0, 0};
         if (!field("m", true, tile.m) || !field("d", true, tile.d) || !field("jobs_per_group", false, tile.jobs_per_group) ||
             !field("groups_per_task", false, tile.groups_per_task) ||
-            !field("add_items_per_task", false, tile.add_items_per_task))
-            return std::string("tune cache ") + path + ": a tile needs integer m, d and tile fields";
+            !field("add_items_per_task", false, tile.add_items_per_task) || !field("deal", false, tile.deal) ||
+            tile.deal > 2)
+            return std::string("tune cache ") + path + ": a tile needs integer m, d and tile fields (deal 0, 1 or 2)";
         tiles.push_back(tile);
     }
     return "";
@@ -492,6 +503,8 @@ int plan_batch_tiles(const mdpe_plan *const *plans, int count, const mdpe_batch_
                      mdpe_batch **out) {
     if (!plans || !out || count <= 0) return bfail(MDPE_EINVAL, "plans, count > 0 and out are required");
     if (ntiles < 0 || (ntiles > 0 && !tiles)) return bfail(MDPE_EINVAL, "bad tiles");
+    for (int q = 0; q < ntiles; ++q)
+        if (tiles[q].deal < 0 || tiles[q].deal > 2) return bfail(MDPE_EINVAL, "a tile's deal must be 0, 1 or 2");
     *out = nullptr;
     std::unique_ptr<mdpe_batch> B(new (std::nothrow) mdpe_batch());
     if (!B) return bfail(MDPE_ENOMEM, "host allocation failed");
@@ -518,7 +531,7 @@ int plan_batch_tiles(const mdpe_plan *const *plans, int count, const mdpe_batch_
         return bfail(MDPE_EUNSUPPORTED, "batch precisions must be all equal, or {2, 4}");
     }
     auto tile_for = [&](int m, int d) {
-        mdpe_batch_tile t{m, d, 0, 0, 0};
+        mdpe_batch_tile t{m, d, 0, 0, 0, 0};
         for (int q = 0; q < ntiles; ++q)
             if (tiles[q].m == m && tiles[q].d == d) t = tiles[q];
         if (t.jobs_per_group <= 0) t.jobs_per_group = mdpe::choose_jobs_per_group(d, m);
@@ -604,7 +617,7 @@ int plan_batch_tiles(const mdpe_plan *const *plans, int count, const mdpe_batch_
         I.stride = S.stride;
         I.steps = S.steps;
         I.J = J;
-        I.simple = mdpe::prefer_simple_dealing(P.d, J, P.m, S.steps) ? 1 : 0;
+        I.simple = P.m > 2 ? 0 : t.deal == 1 ? 0 : t.deal == 2 ? 1 : mdpe::prefer_simple_dealing(P.d, J, P.m, S.steps) ? 1 : 0;
         I.m = P.m;
         I.d = P.d;
         I.n = P.n;

@@ -121,6 +121,8 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
 // layers of the fused launch; A is read with vector loads only.
 struct SingleArgs {
     double *A;
+    long ws_doubles;   // > 0: the workspace lives in LDS at lds_ws_off bytes (copied to A at the end)
+    int lds_ws_off;
     const double *coeff, *z;
     double *value, *grad;
     const int2 *stage;
@@ -146,9 +148,12 @@ __global__ __launch_bounds__(1024) void eval_single_kernel(SingleArgs a) {
     const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, waves = nt >> 6;
     const int d1 = a.d + 1;
+    // the workspace: in LDS when it fits (every phase after staging then
+    // reads and writes LDS only), else the caller's buffer
+    double *A = a.ws_doubles > 0 ? (double *)((char *)lds + a.lds_ws_off) : a.A;
     for (long it = tid; it < (long)a.nstage * d1; it += nt) {
         const long e = it / d1;
-        stage_item(a.A, a.coeff, a.z, a.stage[e], (int)(it - e * d1), a.N, a.n, a.d, W);
+        stage_item(A, a.coeff, a.z, a.stage[e], (int)(it - e * d1), a.N, a.n, a.d, W);
     }
     __syncthreads();
     double *mine = (double *)((char *)lds + (long)wave * a.group_bytes);
@@ -159,28 +164,31 @@ __global__ __launch_bounds__(1024) void eval_single_kernel(SingleArgs a) {
         for (int r = lo; r < hi; r += waves * a.J) {
             const int q = r + wave * a.J;
             const int jn = q < hi ? min(a.J, hi - q) : 0;
-            conv_group<M, false, CX, false, false>(a.A, a.conv + (jn > 0 ? q : lo), jn, a.J, a.d, mine, a.chains,
+            conv_group<M, false, CX, false, false>(A, a.conv + (jn > 0 ? q : lo), jn, a.J, a.d, mine, a.chains,
                                                    a.stride, a.steps, lane, lane, a.simple != 0);
         }
         __syncthreads();
     }
     for (long it = tid; it < (long)a.nscale * d1; it += nt) {
         const long q = it / d1;
-        scale_item<M, CX>(a.A, a.scale[q], (int)(it - q * d1), a.d);
+        scale_item<M, CX>(A, a.scale[q], (int)(it - q * d1), a.d);
     }
     __syncthreads();
     for (int r = 0; r < a.nlev; ++r) {
         const long hi = (long)a.add_off[r + 1] * d1;
         for (long it = (long)a.add_off[r] * d1 + tid; it < hi; it += nt) {
             const long p = it / d1;
-            add_item<M, CX>(a.A, a.add[p], (int)(it - p * d1), a.d);
+            add_item<M, CX>(A, a.add[p], (int)(it - p * d1), a.d);
         }
         __syncthreads();
     }
     for (long it = tid; it < (long)(1 + a.n) * d1; it += nt) {
         const int o = (int)(it / d1);
-        gather_item(a.A, a.value, a.grad, a.out[o], o, (int)(it - (long)o * d1), a.n, a.d, W);
+        gather_item(A, a.value, a.grad, a.out[o], o, (int)(it - (long)o * d1), a.n, a.d, W);
     }
+    // the caller's workspace holds every series afterwards, as after the
+    // per-launch path (the reverse pass reads the monomial values there)
+    for (long q = tid; q < a.ws_doubles; q += nt) a.A[q] = A[q];
 }
 
 // planar [m][count][d+1] series src[e] -> slot dst[e] (skipped when -1), for e < count
@@ -548,7 +556,12 @@ int launch_single(const mdpe_plan *pl, double *A, const double *coeff, const dou
     const mdpe::Plan &P = pl->P;
     const int J = P.single_lanes.jobs_per_group;
     const size_t gb = (conv_lds_bytes(P.d, mdpe::lds_doubles_per_coef(mdpe::kCoef<M, CX>), J) + 15) / 16 * 16;
-    const size_t lds = gb * (size_t)P.single_waves;
+    size_t lds = gb * (size_t)P.single_waves;
+    // the workspace in LDS too when it fits beside the job groups
+    const long ws_doubles = P.n_series * (long)(P.d + 1) * mdpe::kCoef<M, CX>;
+    const bool ws_lds = lds + (size_t)ws_doubles * sizeof(double) <= (size_t)mdpe::kMaxLdsBytes;
+    const int ws_off = (int)lds;
+    if (ws_lds) lds += (size_t)ws_doubles * sizeof(double);
     if (lds > (size_t)mdpe::kMaxLdsBytes) return fail(MDPE_EUNSUPPORTED, "single launch: LDS beyond one workgroup's");
     static std::atomic<bool> attr_set[kMaxDevices];
     const int dv = pl->device >= 0 && pl->device < kMaxDevices ? pl->device : 0;
@@ -559,6 +572,8 @@ int launch_single(const mdpe_plan *pl, double *A, const double *coeff, const dou
     }
     mdpe::SingleArgs a;
     a.A = A;
+    a.ws_doubles = ws_lds ? ws_doubles : 0;
+    a.lds_ws_off = ws_off;
     a.coeff = coeff;
     a.z = z;
     a.value = value;

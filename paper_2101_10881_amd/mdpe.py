@@ -73,7 +73,8 @@ class Times(ctypes.Structure):
 
 class BatchTile(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("jobs_per_group", ctypes.c_int32),
-                ("groups_per_task", ctypes.c_int32), ("add_items_per_task", ctypes.c_int32)]
+                ("groups_per_task", ctypes.c_int32), ("add_items_per_task", ctypes.c_int32),
+                ("deal", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -177,9 +178,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _stream(stream):
+def _stream(stream, device=None):
     if stream is None:
         import torch
+        if device is not None:
+            # the raw handle of torch's current stream on that device, without
+            # building a Stream object
+            return ctypes.c_void_p(torch._C._cuda_getCurrentRawStream(device))
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
 
@@ -305,10 +310,10 @@ def plan_polynomial(n, nvars, vars_, d, m, device=0) -> Plan:
     return Plan(n, nvars, vars_, d, m, device)
 
 
-def eval_and_diff(plan: Plan, coeff, z, value, grad, workspace, stream=None):
+def eval_and_diff(plan: Plan, coeff, z, value, grad, workspace, stream=None, device=None):
     """Enqueue one evaluation on `stream` (tensors on the plan's device)."""
     _check(lib().eval_and_diff(plan.handle, _ptr(coeff), _ptr(z), _ptr(value), _ptr(grad), _ptr(workspace),
-                               _stream(stream)))
+                               _stream(stream, device)))
 
 
 def eval_and_diff_noalloc(plan: Plan, coeff, z, value, grad, stream=None):
@@ -456,18 +461,27 @@ class Polynomial:
 
     def eval_and_diff(self, coeff, z, value=None, grad=None, stream=None, profiler=None, workspace=None):
         import torch
-        self._check_inputs(coeff, z)
         ws = self.workspace if workspace is None else workspace
         if value is None:
             value = torch.empty(self._lead + (self.d + 1,), dtype=torch.float64, device=self.device)
         if grad is None:
             grad = torch.empty(self._lead + (self.n, self.d + 1), dtype=torch.float64, device=self.device)
-        for name, t, shape in (("value", value, self._lead + (self.d + 1,)),
-                               ("grad", grad, self._lead + (self.n, self.d + 1))):
-            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
-                raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
+        # the tensors of the previous call, checked then: repeated calls on the
+        # same buffers (a serving loop) skip the checks; their sizes are fixed
+        # by the plan, and a tensor's storage pointer is compared every call
+        key = (coeff.data_ptr(), z.data_ptr(), value.data_ptr(), grad.data_ptr())
+        last = getattr(self, "_checked", None)
+        if (last is None or last[0] is not coeff or last[1] is not z or last[2] is not value or last[3] is not grad
+                or self._checked_ptrs != key):
+            self._check_inputs(coeff, z)
+            for name, t, shape in (("value", value, self._lead + (self.d + 1,)),
+                                   ("grad", grad, self._lead + (self.n, self.d + 1))):
+                if (t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape
+                        or t.device != self.device):
+                    raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {self.device}")
+            self._checked, self._checked_ptrs = (coeff, z, value, grad), key
         if profiler is None:
-            eval_and_diff(self.plan, coeff, z, value, grad, ws, stream)
+            eval_and_diff(self.plan, coeff, z, value, grad, ws, stream, self.device.index or 0)
         else:
             eval_and_diff_profiled(self.plan, coeff, z, value, grad, ws, profiler, stream)
         return value, grad
@@ -498,7 +512,8 @@ class Batch:
             tarr = (BatchTile * max(len(tl), 1))()
             for q, t in enumerate(tl):
                 tarr[q] = BatchTile(int(t["m"]), int(t["d"]), int(t.get("jobs_per_group", 0)),
-                                    int(t.get("groups_per_task", 0)), int(t.get("add_items_per_task", 0)))
+                                    int(t.get("groups_per_task", 0)), int(t.get("add_items_per_task", 0)),
+                                    int(t.get("deal", 0)))
             _check(lib().plan_batch_tiles(arr, len(self.plans), tarr, len(tl), ctypes.byref(h)))
         self._h = h
 

@@ -151,6 +151,7 @@ def test_tune_cache_without_this_architecture_gives_the_defaults(tmp_path):
     ('{"gfx950": {"tiles": 3}}', "no tile list"),
     ('{"gfx950": {"tiles": [{"d": 8, "jobs_per_group": 2}]}}', "integer m, d"),
     ('{"gfx950": {"tiles": [{"m": 2, "d": 8, "jobs_per_group": 2.5}]}}', "integer m, d"),
+    ('{"gfx950": {"tiles": [{"m": 2, "d": 8, "deal": 3}]}}', "deal 0, 1 or 2"),
 ])
 def test_bad_tune_caches_are_rejected(tmp_path, text, words):
     ws = _mixed(4)
@@ -169,3 +170,16 @@ def test_batch_workspace_is_the_instances_parts():
     B = mdpe.Batch(plans)
     want = sum((p.info["workspace_bytes"] + 255) // 256 * 256 for p in plans)
     assert B.info()["workspace_bytes"] == want
+
+
+def test_deal_tile_field_changes_no_task():
+    # the coefficient order inside a group (schedule or dealt) changes neither
+    # the tasks nor, on the GPU, the bits (tests/test_gpu_batch.py)
+    ws = _mixed(6)
+    plans = [mdpe.Plan.for_workload(w, device=-1) for w in ws]
+    base = mdpe.Batch(plans, tiles=[]).tasks()
+    for deal in (1, 2):
+        tiles = [{"m": 2, "d": w.d, "deal": deal} for w in ws if w.m == 2]
+        assert np.array_equal(mdpe.Batch(plans, tiles=tiles).tasks(), base)
+    with pytest.raises(mdpe.MdpeError):
+        mdpe.Batch(plans, tiles=[{"m": 2, "d": 8, "deal": 5}])

@@ -111,6 +111,11 @@ def test_batch_graph_replays_follow_inputs():
      {"m": 4, "d": 33, "jobs_per_group": 2, "groups_per_task": 5, "add_items_per_task": 333}],
     [{"m": m, "d": d, "jobs_per_group": 1, "groups_per_task": 1, "add_items_per_task": 4096}
      for m in (2, 4) for d in (0, 3, 8, 16, 33, 64)],
+    # double doubles forced onto the lane schedule, and dealt to lanes in turn
+    [{"m": 2, "d": d, "jobs_per_group": 3, "groups_per_task": 2, "add_items_per_task": 1000, "deal": 1}
+     for d in (0, 3, 8, 16, 33, 64)],
+    [{"m": 2, "d": d, "jobs_per_group": 5, "groups_per_task": 3, "add_items_per_task": 777, "deal": 2}
+     for d in (0, 3, 8, 16, 33, 64)],
 ])
 def test_tiles_do_not_change_bits(tiles):
     ws = _instances(12, 4)

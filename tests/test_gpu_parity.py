@@ -288,3 +288,30 @@ def test_hip_graph_capture_and_replay(oracle_lib):
         want_v, want_g = oracle_lib.eval_workload(w)
         assert_bitexact(value.cpu().numpy(), want_v, f"replay {rep} value")
         assert_bitexact(grad.cpu().numpy(), want_g, f"replay {rep} gradient")
+
+
+def test_repeated_calls_and_argument_checks(oracle_lib):
+    # repeated calls on the same buffers skip the Python-side checks; new or
+    # wrong tensors are still checked, and every call recomputes
+    import torch
+    from paper_2101_10881_amd import mdpe
+    w = W.rand3()
+    dev = torch.device("cuda", 0)
+    P = mdpe.Polynomial.for_workload(w, dev)
+    coeff = torch.from_numpy(w.coeff).to(dev)
+    z = torch.from_numpy(w.z).to(dev)
+    v, g = P.eval_and_diff(coeff, z)
+    want_v, want_g = oracle_lib.eval_workload(w)
+    for _ in range(3):
+        v.fill_(0.0)
+        P.eval_and_diff(coeff, z, v, g)
+        torch.cuda.synchronize()
+        assert_bitexact(v.cpu().numpy(), want_v, "value")
+        assert_bitexact(g.cpu().numpy(), want_g, "gradient")
+    with pytest.raises(ValueError):
+        P.eval_and_diff(coeff[:, :-1].contiguous(), z, v, g)
+    with pytest.raises(ValueError):
+        P.eval_and_diff(coeff, z, v[:, :-1].contiguous(), g)
+    P.eval_and_diff(coeff, z, v, g)
+    torch.cuda.synchronize()
+    assert_bitexact(v.cpu().numpy(), want_v, "value after the refused calls")
