@@ -59,7 +59,14 @@ __device__ __forceinline__ void chain_decode(ChainState &st, int jn) {
 // (p2 10d, d = 152), 15% slower for groups of several jobs per wavefront
 // (p2 10d, d = 63; p1 8d, d = 32), equal on p1 10d at d = 152; the kernel
 // chooses per instantiation.
-template <int M, bool CORR, bool CX = false, bool XS = false, bool CODE_AHEAD = false>
+// DESC_FIRST: how the operands are staged (below).  Descriptors first, with a
+// small group copied in one flat round, takes 16 products of three of eight
+// variables at two doubles and d = 8 (a single launch) from 0.027 to 0.018 ms.
+// Elsewhere it measured even or slower (per-layer launches of p1 at eight
+// doubles and d = 32, the batched kernel), and in the fused and single-launch
+// kernels it took 20-40 more registers from three doubles on; only the single
+// launch at one or two doubles per coefficient uses it.
+template <int M, bool CORR, bool CX = false, bool XS = false, bool CODE_AHEAD = false, bool DESC_FIRST = false>
 __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *__restrict__ jobs, int jn, int J,
                                            int d, double *lds, const int *__restrict__ chains, int stride,
                                            int steps, int lane, int row, bool simple = false, int nrows = kLanes) {
@@ -76,20 +83,70 @@ __device__ __forceinline__ void conv_group(double *__restrict__ A, const int4 *_
     // in L2 -- except for coefficients of at most two doubles, where a step is
     // so short that its latency would dominate: then it is staged too.  The
     // first operand is read one step ahead of its use, the second two steps.
-    for (int j = 0; j < jn; ++j) {
-        const int4 t = jobs[j];
-        if (!XS) {
-            const double *xs = A + (long)t.x * S;
-            for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+    if (!DESC_FIRST) {
+        // job by job: lane 0 writes the descriptor, all lanes copy the operands
+        for (int j = 0; j < jn; ++j) {
+            const int4 t = jobs[j];
+            if (!XS) {
+                const double *xs = A + (long)t.x * S;
+                for (long q = lane; q < S; q += 64) X[j * S + q] = xs[q];
+            }
+            if (YL) {
+                const double *ys = A + (long)t.y * S;
+                for (long q = lane; q < S; q += 64) Y[j * S + q] = ys[q];
+            }
+            if (lane == 0) jd[j] = JobOffsets{(long)t.x * S, (long)t.y * S, (long)t.z * S, 0};
         }
-        if (YL) {
-            const double *ys = A + (long)t.y * S;
-            for (long q = lane; q < S; q += 64) Y[j * S + q] = ys[q];
+        __syncthreads();
+    } else {
+        // The descriptors first, one per lane; then a group whose staged doubles
+        // fit one round of kStageLoads per lane (many small jobs, as at low
+        // degree) is copied as one flat range with all its loads in flight
+        // before the LDS stores: a few memory latencies instead of one per job.
+        // (X and Y are job-major with stride S: flat element g is double g mod S
+        // of job g / S.)  Larger groups are copied job by job.
+        for (int j = lane; j < jn; j += 64) {
+            const int4 t = jobs[j];
+            jd[j] = JobOffsets{(long)t.x * S, (long)t.y * S, (long)t.z * S, 0};
         }
-        if (lane == 0) jd[j] = JobOffsets{(long)t.x * S, (long)t.y * S, (long)t.z * S, 0};
+        __syncthreads();
+        constexpr int kStageLoads = YL ? 4 : 8;
+        const int Si = (int)S, total = jn * Si;
+        if (!XS && total <= 64 * kStageLoads) {
+            const int sj = 64 / Si, sq = 64 - sj * Si;
+            int j = lane / Si, q = lane - j * Si;
+            double vx[kStageLoads], vy[kStageLoads];
+#pragma unroll
+            for (int u = 0; u < kStageLoads; ++u) {
+                if (lane + 64 * u < total) {
+                    const JobOffsets &o = jd[j];
+                    vx[u] = A[o.x + q];
+                    if (YL) vy[u] = A[o.y + q];
+                }
+                j += sj;
+                q += sq;
+                if (q >= Si) {
+                    q -= Si;
+                    ++j;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageLoads; ++u)
+                if (lane + 64 * u < total) {
+                    X[lane + 64 * u] = vx[u];
+                    if (YL) Y[lane + 64 * u] = vy[u];
+                }
+        } else if (!XS) {
+            for (int j = 0; j < jn; ++j) {
+                const JobOffsets &o = jd[j];
+                for (long q = lane; q < S; q += 64) X[j * S + q] = A[o.x + q];
+                if (YL)
+                    for (long q = lane; q < S; q += 64) Y[j * S + q] = A[o.y + q];
+            }
+        }
+        if (!XS) __syncthreads();  // every wavefront of the workgroup, whichever copy it took
     }
-    __syncthreads();
-    if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barrier)
+    if (jn <= 0) return;  // a wavefront past the last group (after the workgroup barriers)
 
     if constexpr (W <= 2 && !XS) {
         if (simple) {

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(1024) void eval_single_kernel(SingleArgs a) {
         for (int r = lo; r < hi; r += waves * a.J) {
             const int q = r + wave * a.J;
             const int jn = q < hi ? min(a.J, hi - q) : 0;
-            conv_group<M, false, CX, false, false>(A, a.conv + (jn > 0 ? q : lo), jn, a.J, a.d, mine, a.chains,
+            conv_group<M, false, CX, false, false, (CX ? 2 * M : M) <= 2>(A, a.conv + (jn > 0 ? q : lo), jn, a.J, a.d, mine, a.chains,
                                                    a.stride, a.steps, lane, lane, a.simple != 0);
         }
         __syncthreads();
