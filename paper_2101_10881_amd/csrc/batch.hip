@@ -151,7 +151,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(M2 <= 4 ? 6 
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(32);  // ~2000 cycles: little polling traffic, small against a task
             }
             if (!ok) {
                 if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -271,7 +271,10 @@ int prepare_batch(mdpe_batch *b) {
         BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)mdpe::batch_kernel<M1, M2>, 64,
                                                           b->lds));
         BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-        // every XCD needs resident wavefronts to drain its queue
+        // every XCD needs resident wavefronts to drain its queue; a CU's four
+        // SIMDs get equal numbers (17 resident per CU put five on one SIMD,
+        // whose tasks ran slowest: 16 measured 0.6% faster on the mixed batch)
+        if (per_cu > 4) per_cu -= per_cu % 4;
         b->grid = std::max(1, per_cu) * cus;
     }
     return MDPE_OK;
