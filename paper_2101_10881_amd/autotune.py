@@ -55,6 +55,7 @@ def main():
     ap.add_argument("--seeds", default="2,3,4", help="mixed batches timed together (the benchmark uses seed 1)")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--passes", type=int, default=1)
+    ap.add_argument("--start", default=None, help="a tune cache whose tiles the descent starts from")
     a = ap.parse_args()
     import torch
     dev = torch.device("cuda", 0)
@@ -98,6 +99,12 @@ def main():
     chosen = {}
     default_ms = best_ms = evaluate([])
     print(f"default tiles: {default_ms:.3f} ms", flush=True)
+    if a.start:
+        with open(a.start) as f:
+            start = json.load(f).get(ARCH, {}).get("tiles", [])
+        chosen = {(t["m"], t["d"]): t for t in start}
+        best_ms = evaluate(list(chosen.values()))
+        print(f"start tiles: {best_ms:.3f} ms", flush=True)
     for _ in range(a.passes):
         for key in buckets:
             for cand in candidates(*key):

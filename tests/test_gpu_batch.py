@@ -220,3 +220,18 @@ def test_eval_and_diff_batch_rebinds_on_the_stream(oracle_lib):
     v, g = oracle_lib.eval_workload(ws[3])
     assert_bitexact(outs[0][0][3].cpu().numpy(), v, "oracle value 3")
     assert_bitexact(outs[0][1][3].cpu().numpy(), g, "oracle grad 3")
+
+
+def test_default_grid_fills_whole_simds():
+    # the persistent grid is the resident one-wavefront workgroups per CU rounded
+    # down to a multiple of the CU's four SIMDs (equal wavefronts per SIMD)
+    import torch
+    ws = _instances(6, 9)
+    want = _plain(ws)
+    got, B = _batched(ws)
+    _check(got[0], want, "default grid")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    grid = B.batch.info()["grid"]
+    assert grid % cus == 0, (grid, cus)
+    per_cu = grid // cus
+    assert per_cu <= 4 or per_cu % 4 == 0, per_cu
