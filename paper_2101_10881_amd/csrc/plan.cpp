@@ -743,7 +743,13 @@ static double make_chain_plan(Plan &P, const std::vector<std::vector<int64_t>> &
     // schedule step (measured on p2 at d = 8..152 against the dealt plans)
     const double step = P.w == 1 ? 0.55 : 1.0;
     const double chain_cost = rounds * worst * k * eff * (1.0 + 0.02 * 4.0 / S) * step;
-    return chain_cost + layer_cost(P, P.lanes.waves_per_job, P.lanes.jobs_per_group, P.lanes.steps, 1.0, Lmax + 1);
+    // the layers after the chains (p2's cross products), dealt or by the lane
+    // schedule as choose_staged_lanes set them, weighed as the plan without a
+    // chain launch weighs its steps
+    const int Q = P.lanes.waves_per_job, J = P.lanes.jobs_per_group;
+    const double rest = P.simple ? layer_cost(P, Q, J, dealt_steps(P.d, J, Q), P.w == 1 ? 0.15 : 0.4, Lmax + 1)
+                                 : layer_cost(P, Q, J, P.lanes.steps, 1.0, Lmax + 1);
+    return chain_cost + rest;
 }
 
 // LDS slots of first operands a chain workgroup gets: up to 96 KiB of LDS
@@ -759,10 +765,10 @@ static int chain_ring_slots(const Plan &P, int Lmax) {
 // 8, 12, 16 wavefronts and barriers every S = 1, 2, 4 steps, applied when forced or
 // estimated under 0.9 of `other` (the cost of the plan without it).  On p2
 // (64 products per chain) that is every precision from two doubles on at
-// d = 8..152 (measured 1.3-7.4x faster) and one double at d = 31 and 64
-// (1.2-1.6x); one double at d >= 95 keeps its dealt per-layer plan (the
-// chain launch measured 1.3-1.9x slower there).  Returns whether P now holds
-// a chain launch.
+// d = 8..191 (measured 1.3-7.4x faster) and one double at d = 31..152
+// (1.1-1.6x); one double at d = 191 keeps its dealt per-layer plan (the chain
+// launch measured 7% slower there).  Returns whether P now holds a chain
+// launch.
 static constexpr bool kChainByDefault = true;
 
 static bool choose_chain_launch(Plan &P, bool forced, double other) {
