@@ -48,6 +48,32 @@ def candidates(m: int, d: int):
         yield {"m": m, "d": d, "jobs_per_group": J, "groups_per_task": G, "add_items_per_task": A, "deal": D}
 
 
+def neighbours(m: int, d: int, tile: dict):
+    """Tiles one field away from `tile` (the default tile's fields where it has none): jobs per
+    group and groups per task by factors 1/2, 2/3, 3/4, 4/3, 3/2 and 2, addition items halved
+    or doubled, and the other coefficient orders at two doubles."""
+    base = {"m": m, "d": d, "jobs_per_group": tile.get("jobs_per_group") or default_jobs_per_group(d),
+            "groups_per_task": tile.get("groups_per_task") or 0, "add_items_per_task": tile.get("add_items_per_task") or 4096,
+            "deal": tile.get("deal", 0)}
+    seen = {tuple(sorted(base.items()))}
+    def out(t):
+        k = tuple(sorted(t.items()))
+        if k not in seen:
+            seen.add(k)
+            yield dict(t)
+    for f in (0.5, 2 / 3, 0.75, 4 / 3, 1.5, 2.0):
+        J = max(1, min(64, round(base["jobs_per_group"] * f)))
+        yield from out({**base, "jobs_per_group": J})
+        G = max(1, round((base["groups_per_task"] or 4) * f))
+        yield from out({**base, "groups_per_task": G})
+    for A in (base["add_items_per_task"] // 2, base["add_items_per_task"] * 2):
+        if A >= 256:
+            yield from out({**base, "add_items_per_task": A})
+    if m <= 2:
+        for D in (0, 1, 2):
+            yield from out({**base, "deal": D})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="tune_cache.json")
@@ -56,6 +82,8 @@ def main():
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--passes", type=int, default=1)
     ap.add_argument("--start", default=None, help="a tune cache whose tiles the descent starts from")
+    ap.add_argument("--refine", action="store_true",
+                    help="try each field's neighbours of the current tile (finer steps) instead of the full grid")
     a = ap.parse_args()
     import torch
     dev = torch.device("cuda", 0)
@@ -107,7 +135,7 @@ def main():
         print(f"start tiles: {best_ms:.3f} ms", flush=True)
     for _ in range(a.passes):
         for key in buckets:
-            for cand in candidates(*key):
+            for cand in (neighbours(*key, chosen.get(key, {})) if a.refine else candidates(*key)):
                 trial = dict(chosen)
                 trial[key] = cand
                 ms = evaluate(list(trial.values()))
