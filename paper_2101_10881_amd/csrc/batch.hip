@@ -12,7 +12,7 @@
 // one queue, except for an instance costing more than an eighth of the batch
 // (a batch of one), whose tasks are dealt over all queues in turn.  Each
 // queue is ordered by pipeline depth.  One persistent kernel of one-wavefront workgroups (as many as
-// are resident) reads the XCD it runs on from the XCC_ID hardware register
+// are resident, rounded down to equal numbers per SIMD) reads the XCD it runs on from the XCC_ID hardware register
 // and claims tasks of that XCD's queue with an atomic counter, so an
 // instance's data stays near one L2.  A task of stage s of instance p waits
 // until p's completion counter reaches the number of p's tasks in stages
