@@ -324,9 +324,13 @@ int check_plan_jobs(int32_t n, int32_t N, int64_t n_series, const int32_t *conv_
  *             its contents are scratch and may be reused between calls
  *             that are ordered on one stream
  *   stream    hipStream_t or NULL
- * Launches: one staging kernel, one convolution kernel per layer, one scale
- * kernel when an exponent exceeds one, one addition kernel per level, one
- * gather kernel.  Calls on different streams must not share a workspace.
+ * Launches: one staging kernel; the convolutions as the plan chose them
+ * (plan_info): one kernel per layer, one fused launch of every layer
+ * (fused_components > 0), or the chain launch followed by one kernel per
+ * remaining layer (chain_layers > 0); one scale kernel when an exponent exceeds
+ * one; one addition kernel per level; one gather kernel.  A plan with
+ * single_launch = 1 runs all of it in one kernel.  Calls on different streams
+ * must not share a workspace.
  */
 int eval_and_diff(const mdpe_plan *plan, const double *coeff, const double *z, double *value,
                   double *grad, void *workspace, void *stream);
