@@ -275,3 +275,17 @@ def test_chain_launch_only_where_asked_or_worth_it():
     assert mdpe.Plan.for_workload(shallow, device=-1).info["chain_layers"] == 0
     assert mdpe.Plan.for_workload(W.p2(m=4, d=64), device=-1,
                                   flags=mdpe.MDPE_LAYER_LAUNCHES).info["chain_layers"] == 0
+
+
+def test_chain_launch_default_at_one_and_two_doubles():
+    # the layers after the chains (p2's cross products) are weighed as the plan
+    # without the chain launch weighs its dealt steps; measured on MI355X, the
+    # chain launch wins at one double for d = 31..152 (not at d = 127, 0.88 of
+    # the dealt plan's time against an estimate of 0.98) and at two doubles for
+    # every degree, d = 191 included (0.94 against 1.92 ms); at one double and
+    # d = 191 it loses (7%)
+    def chained(m, d):
+        return mdpe.Plan.for_workload(W.p2(m=m, d=d), device=-1).info["chain_layers"] > 0
+    assert all(chained(1, d) for d in (31, 63, 95, 152))
+    assert not chained(1, 191)
+    assert all(chained(2, d) for d in (31, 63, 95, 127, 152, 191))
