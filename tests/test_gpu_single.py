@@ -61,6 +61,8 @@ def test_edge_cases(oracle_lib):
 
 def test_complex_and_exponents(oracle_lib):
     _single_vs_oracle(oracle_lib, W.random_poly("single_cx", 3, 7, 6, 10, [3] * 10, seed=8, cx=True))
+    # one double per part: two doubles per coefficient, staged descriptors first
+    _single_vs_oracle(oracle_lib, W.random_poly("single_cx1", 1, 9, 6, 14, [3] * 14, seed=7, cx=True))
     _single_vs_oracle(oracle_lib, W.with_exponents(W.random_poly("single_e", 2, 6, 5, 9, [3] * 9, seed=9), 4, seed=2))
 
 
